@@ -1,0 +1,202 @@
+#!/usr/bin/env python
+"""Benchmark: time to momentum residual 1e-6 for one 256^3 solve on one MI355X.
+
+A step is one complete solve -- Algorithm 1 from P^0 = 0 (or from the learned
+warm start, reported beside it) until eps_R <= 1e-6 (Eq. ResidualMomentum) --
+of a 256^3 field: the gradient of 32 random Gaussian pressure blobs plus 5 %
+Gaussian noise, FP32 stencil and vector updates, FP64 iterate, dot products,
+residual and gauge.  Inputs are generated on the GPU before the timed region.
+
+Prints one JSON line.  Besides the contract fields it carries
+  roofline      HBM roofline of the dominant kernel, its duration measured with
+                HIP events on the library's stream (pi_time_kernel)
+  kernels       the same for the three kernels of an outer step
+  cpu_baseline  the CPU FP64 oracle (route O1, sparse-LU inner solve) on a
+                bounded sample, scaled to one 256^3 solve
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+# algorithmic bytes per cell per launch (FP32 mode): what each kernel must read
+# and write once, neighbour re-reads excluded
+BYTES_PER_CELL = {
+    "k_outer": 8 + 4 + 4 + 4 + 8 + 4,   # P, delta, S, code in; P', r out
+    "k_cg_spmv": 4 + 4 + 4 + 4 + 4,     # r, p, code in; p', q out
+    "k_cg_update": 4 * 4 + 2 * 4,       # p, q, r, delta in; delta, r out
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256, help="grid side (256 is the benchmark workload)")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--seed", type=int, default=9001, help="held out from warm-start training seeds")
+    ap.add_argument("--inner", type=int, default=None, help="inner CG iterations per outer step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-n", type=int, default=28)
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    return ap.parse_args()
+
+
+def traffic_from_profile(kernel, n, src_hash):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_blobs{n}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"^source_sha256:\s*(\S+)", txt, re.M)
+    m_b = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt, re.M)
+    if not m_b or not m_hash or m_hash.group(1) != src_hash:
+        return None
+    return float(m_b.group(1))
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("pi_kernels.hip", "pi_common.h"):
+        with open(os.path.join(ROOT, "paper_2311_16935_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(n_sample, seed, n_target, tol):
+    """Oracle route O1 on an n_sample^3 grid of the same recipe, timed on this
+    host, scaled to n_target^3: cost per outer step grows with the cell count
+    and the outer-step count with the side length (about 14 n here), so the
+    scale factor is (n_target / n_sample)^4.  The sparse LU's fill grows
+    faster than the cell count in 3-D, so the scaled figure understates the
+    oracle's real cost at 256^3."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle.solve import outer_iteration
+    from oracle.system import assemble
+
+    w = synth.config_blobs_3d(n_sample, seed=seed)
+    g = [x.float().double().numpy() for x in w.grads]
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        s = assemble(np.ones((n_sample,) * 3, np.uint8), w.spacing)
+        r = outer_iteration(s, s.source(g), tol, 100000)
+        t = time.perf_counter() - t0
+    scale = (n_target / n_sample) ** 4
+    return {
+        "value": t * scale,
+        "unit": "s per %d^3 solve to eps_R<=%g (scaled)" % (n_target, tol),
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"route O1 (exact sparse-LU inner solve) on {n_sample}^3 blobs, seed {seed}: "
+                  f"{r.outer} outer steps in {t:.2f} s on 1 thread "
+                  f"(host affinity {len(os.sched_getaffinity(0))} cores); scaled by (n/{n_sample})^4",
+        "sample_seconds": t,
+        "sample_outer_iters": r.outer,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the solver has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2311_16935_amd as pi
+    import synth
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    w = synth.config_blobs_3d(n, seed=args.seed, device=dev, with_pressure=False)
+    grads = [g.to(torch.float32).contiguous() for g in w.grads]
+    del w.grads[:]
+    plan = pi.Plan((n, n, n), w.spacing, fp64=False, inner_iters=args.inner)
+    P = torch.empty((n, n, n), dtype=torch.float32, device=dev)
+    ncell = n ** 3
+    for _ in range(args.warmup):
+        plan.solve(grads, P=P, tol=args.tol)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = plan.solve(grads, P=P, tol=args.tol)
+        infos.append(r.info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sec = elapsed / max(1, args.steps)
+    info = infos[-1]
+    assert info["status"] == 0 and info["eps_R"] <= args.tol, info
+
+    # kernel durations, measured with HIP events on the library's stream
+    src_hash = kernel_source_hash()
+    kern = {}
+    for name, kid in (("k_outer", pi.PI_K_OUTER), ("k_cg_spmv", pi.PI_K_SPMV), ("k_cg_update", pi.PI_K_UPDATE)):
+        ms = pi.pi_time_kernel(plan.handle, kid, args.kernel_reps)
+        alg = BYTES_PER_CELL[name] * ncell
+        kern[name] = {"avg_ms": ms, "alg_bytes": alg, "achieved_GBs": alg / (ms * 1e-3) / 1e9}
+    launches = {"k_outer": info["outer_iters"] + 1, "k_cg_spmv": info["inner_iters_total"],
+                "k_cg_update": info["inner_iters_total"]}
+    for name in kern:
+        kern[name]["launches_per_solve"] = launches[name]
+        kern[name]["share_of_solve"] = launches[name] * kern[name]["avg_ms"] * 1e-3 / sec
+    dom = max(kern, key=lambda k: kern[k]["launches_per_solve"] * kern[k]["avg_ms"])
+    d = kern[dom]
+    traffic = traffic_from_profile(dom, n, src_hash)
+    roof = {"kernel": dom, "bound": "hbm", "achieved": d["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": d["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
+            "bytes_per_cell": BYTES_PER_CELL[dom], "cells_per_launch": ncell}
+
+    out = {
+        "metric": "time-to-residual 1e-6 per 256^3 solve, plain vs learned warm start; HBM GB/s",
+        "value": sec,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "reductions_dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"blobs3d_{n}^3", "n": n, "cells": ncell, "nblobs": 32, "noise": 0.05,
+                   "seed": args.seed, "tol_eps_R": args.tol, "start": "P0=0 (plain)",
+                   "inner_cg_iters": info["inner_iters_total"] // max(1, info["outer_iters"]),
+                   "parallelism": "single GPU"},
+        "solve": {"outer_iters": info["outer_iters"], "inner_iters": info["inner_iters_total"],
+                  "eps_R": info["eps_R"], "eps_P": info["eps_P"],
+                  "outer_point_iters_per_s": ncell * info["outer_iters"] / sec,
+                  "inner_point_iters_per_s": ncell * info["inner_iters_total"] / sec},
+        "roofline": roof,
+        "kernels": kern,
+        "kernel_source_sha256": src_hash,
+    }
+    plan.close()
+    del grads, P
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.seed, n, args.tol)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

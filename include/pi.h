@@ -1,0 +1,203 @@
+/*
+ * pi.h -- C interface of libpi, an MI355X (gfx950) solver for matrix-based
+ * omnidirectional pressure integration (Zigunov & Charonko, arXiv 2311.16935).
+ *
+ * Problem (Section "The Matrix-based Omnidirectional Integration Method"):
+ * given a pressure-gradient field f on a uniform rectangular 2-D or 3-D grid
+ * of cells, some of which hold no data, find the pressure P (up to one
+ * constant per connected group of data cells) by iterating Eq. MatrixEquation
+ *     [W^{n+1}] {P^{n+1}} = [W^n] {P^n} + {S}
+ * from {P^0} (Algorithm 1) until the momentum residual of
+ * Eq. ResidualMomentum falls to a threshold.  The weights come from the ray
+ * counters of Eqs. AEnp1, AEn, ANnp1, ANn, Acn (2-D) and their 3-D analogues;
+ * {S} is the source sum of Eq. ExplicitEqn_FaceCrossing.
+ *
+ * Conventions shared by every call:
+ *  - Grid sizes are (nx, ny[, nz]); arrays are dense, x fastest:
+ *    cell (x, y, z) lives at x + nx * (y + ny * z).
+ *  - Directions: E = +x, W = -x, N = +y, S = -y, F = +z, B = -z.
+ *  - The mask is one byte per cell, 1 = data present, 0 = missing; cells
+ *    outside the grid count as missing.
+ *  - "Device pointer" means memory from hipMalloc (or a torch CUDA tensor) on
+ *    the current HIP device; the library never frees caller memory.
+ *  - Precision: with PI_FP32 the gradients and P are float; the operator
+ *    apply and the inner Krylov updates run in float, while P is carried in
+ *    double internally and every dot product, norm and the gauge are
+ *    accumulated in double.  With PI_FP64 everything is double.
+ *  - Every call returns a pi_status; no C++ exception crosses the interface.
+ *    Calls on one plan are not thread-safe; distinct plans are independent.
+ *  - stream is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued asynchronously unless stated otherwise.
+ */
+#ifndef PI_H
+#define PI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pi_status {
+  PI_OK = 0,
+  PI_ERR_INVALID_ARG = 1,   /* a size, spacing, pointer or flag is invalid     */
+  PI_ERR_OOM = 2,           /* device or host allocation failed                */
+  PI_ERR_NONFINITE = 3,     /* a data cell holds a NaN or infinite gradient    */
+  PI_ERR_NOT_CONVERGED = 4, /* max_iter outer steps without reaching tol       */
+  PI_ERR_DIVERGED = 5,      /* the residual became non-finite                  */
+  PI_ERR_DEVICE = 6         /* a HIP runtime call failed                       */
+} pi_status;
+
+typedef struct pi_plan_s *pi_plan_t;
+
+/* pi_plan flags */
+#define PI_FP32 0x0u
+#define PI_FP64 0x1u
+#define PI_INNER_CG 0x0u        /* conjugate gradient, as in the paper's GPU code */
+#define PI_INNER_BICGSTAB 0x2u  /* stabilised BiCG, safe for the nonsymmetric M  */
+
+/* pi_solve flags */
+#define PI_WARM_START 0x1u      /* P holds P^0 on entry (else P^0 = 0)            */
+
+/* operators for pi_apply */
+#define PI_OP_M 0  /* [W^{n+1}] = I - W^{n+1}                                    */
+#define PI_OP_N 1  /* [W^n] = W^n (diagonal w_C^n)                               */
+#define PI_OP_L 2  /* [W^{n+1}] - [W^n], whose residual Eq. ResidualMomentum uses */
+
+typedef struct pi_info {
+  int64_t outer_iters;       /* solves of Eq. MatrixEquation performed          */
+  int64_t inner_iters_total; /* inner Krylov iterations over all outer steps    */
+  double eps_R;              /* Eq. ResidualMomentum at the returned P          */
+  double eps_P;              /* Eq. ResidualPressure of the last outer step     */
+  double ms;                 /* wall time of the call, host clock, milliseconds */
+  int32_t status;            /* pi_status of this instance                      */
+  int32_t components;        /* connected groups of data cells                  */
+} pi_info;
+
+/*
+ * pi_plan -- analyse a grid once: ray-count constants (Eq. cxx2D in 2-D;
+ * Eqs. FarFaceEquation and IAc..ICc by quadrature in 3-D, or the closed forms
+ * of Eqs. ConstantFarFace / ConstantNearFaces when dx = dy = dz), the packed
+ * per-cell counter codes, the connected groups of data cells, and all device
+ * workspace.
+ *   ndim     2 or 3.
+ *   dims     host array {nx, ny, nz}; nz is ignored when ndim == 2.  Each >= 1
+ *            and the cell count nx*ny*nz below 2^31.
+ *   spacing  host array {dx, dy, dz}, finite and > 0 (dz ignored in 2-D).
+ *   mask     host pointer to nx*ny*nz bytes (copied), or NULL = all cells hold
+ *            data.  At least one cell must hold data.
+ *   flags    PI_FP32 or PI_FP64, ORed with PI_INNER_CG or PI_INNER_BICGSTAB.
+ *   out      receives the plan; set to NULL on failure.
+ * Errors: PI_ERR_INVALID_ARG, PI_ERR_OOM, PI_ERR_DEVICE.  Synchronous.
+ */
+pi_status pi_plan(int ndim, const int64_t dims[3], const double spacing[3], const uint8_t *mask,
+                  uint32_t flags, pi_plan_t *out);
+
+/* Release a plan and its device workspace (NULL is ignored).  Synchronous. */
+void pi_plan_destroy(pi_plan_t plan);
+
+/* Device bytes held by the plan. */
+size_t pi_workspace_bytes(pi_plan_t plan);
+
+/*
+ * Inner-solve policy: `iters` Krylov iterations per outer step (1..4096;
+ * default 8 in 2-D, 4 in 3-D).  The paper leaves the inner tolerance open; the
+ * fixed point of the outer iteration does not depend on this choice, only the
+ * trajectory does.
+ */
+pi_status pi_set_inner_iters(pi_plan_t plan, int32_t iters);
+
+/*
+ * Tile shape: every wave marches `mseg` planes (3-D) or rows (2-D) of a
+ * 64-cell strip; 0 restores the size-based default.  The autotuner sweeps
+ * this knob.  pi_get_tile returns the current value.
+ */
+pi_status pi_set_tile(pi_plan_t plan, int32_t mseg);
+int32_t pi_get_tile(pi_plan_t plan);
+
+/*
+ * pi_solve -- Algorithm 1 on one grid.
+ *   gx, gy, gz  device pointers to the gradient components (gz NULL in 2-D),
+ *               float or double per the plan.  Values in masked cells are
+ *               never read as data (NaN is allowed there).
+ *   P           device pointer, same type: in = P^0 when PI_WARM_START is set
+ *               (values in masked cells ignored); out = the returned pressure
+ *               with the mean removed over every connected group of data
+ *               cells (a data cell with no data neighbour gets 0); masked
+ *               cells are set to NaN.
+ *   tol         stop when eps_R <= tol (Eq. ResidualMomentum, relative to
+ *               ||S||); tol >= 0.
+ *   max_iter    upper bound on outer steps (>= 0).
+ *   info        host pointer (may be NULL) filled when the call returns.
+ * The call returns once the solve has finished on `stream` (it polls the
+ * convergence flag); P is then valid.  If ||S|| = 0 the exact answer is a
+ * constant, so P = 0 is returned in every data cell with eps_R = 0.  In FP32
+ * mode eps_R refers to the FP64 iterate; rounding the returned field to float
+ * alone leaves a residual of order 1e-7 * ||[W^{n+1}]-[W^n]|| ||P|| / ||S||.
+ * If max_iter is reached first, the last iterate is returned (gauged)
+ * together with PI_ERR_NOT_CONVERGED.
+ * Errors: PI_ERR_INVALID_ARG, PI_ERR_NONFINITE, PI_ERR_NOT_CONVERGED,
+ * PI_ERR_DIVERGED, PI_ERR_DEVICE.
+ */
+pi_status pi_solve(pi_plan_t plan, const void *gx, const void *gy, const void *gz, void *P,
+                   double tol, int64_t max_iter, uint32_t flags, pi_info *info, void *stream);
+
+/*
+ * pi_solve_batched -- many independent grids of uneven size in one set of
+ * launches: every kernel of an outer step walks a work list of tiles drawn
+ * from all still-active instances, scalars and the convergence flag are kept
+ * per instance, converged instances drop out of the work list, and one outer
+ * step is captured as a HIP graph and replayed.
+ *   count         number of instances (>= 1); plans[i] must be distinct and
+ *                 share the precision flag.
+ *   gx, gy, gz, P host arrays of `count` device pointers, as for pi_solve
+ *                 (gz may be NULL, or hold NULL for 2-D instances).
+ *   tol           host array of `count` thresholds.
+ *   infos         host array of `count` pi_info (may be NULL).
+ * Returns the worst per-instance status (per-instance codes in infos[i]).
+ */
+pi_status pi_solve_batched(int64_t count, const pi_plan_t *plans, const void *const *gx,
+                           const void *const *gy, const void *const *gz, void *const *P,
+                           const double *tol, int64_t max_iter, uint32_t flags, pi_info *infos,
+                           void *stream);
+
+/*
+ * pi_source -- the source vector {S} (Eq. ExplicitEqn_FaceCrossing, last sum)
+ * on the grid: S is a device array of nx*ny*nz float/double, 0 in masked
+ * cells.  Returns PI_ERR_NONFINITE (after a stream sync) if a data cell holds
+ * a non-finite gradient.
+ */
+pi_status pi_source(pi_plan_t plan, const void *gx, const void *gy, const void *gz, void *S,
+                    void *stream);
+
+/*
+ * pi_apply -- y = op x for op in {PI_OP_M, PI_OP_N, PI_OP_L} (the operators
+ * of Eq. MatrixEquation), x and y device arrays of nx*ny*nz elements of the
+ * plan's type; entries of x in masked cells are ignored, y is 0 there.
+ * x and y must not overlap.  Asynchronous.
+ */
+pi_status pi_apply(pi_plan_t plan, int op, const void *x, void *y, void *stream);
+
+/*
+ * pi_time_kernel -- measurement hook: launch one of the solve's kernels
+ * `reps` times back to back on `stream`, exactly as the solve launches it
+ * (same code, grid and data), bracketed by HIP events recorded on that
+ * stream, and return the mean duration per launch in *avg_ms.  kernel is
+ * PI_K_OUTER, PI_K_SPMV or PI_K_UPDATE.  Meant to run after a pi_solve on the
+ * same plan and gradients (the workspace then holds solve data); it
+ * overwrites the plan's workspace.  Synchronous.
+ */
+#define PI_K_OUTER 0   /* outer residual and update, Eq. ResidualMomentum      */
+#define PI_K_SPMV 1    /* inner search direction and M p                       */
+#define PI_K_UPDATE 2  /* inner correction and residual update                 */
+pi_status pi_time_kernel(pi_plan_t plan, int kernel, int32_t reps, double *avg_ms, void *stream);
+
+/* Human-readable name of a status code (static storage). */
+const char *pi_status_string(pi_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PI_H */

@@ -1,0 +1,117 @@
+// Shared host/device definitions of libpi.
+//
+// Work decomposition.  A grid is cut into "strips": 64 consecutive cells
+// along x (one wavefront, one cell per lane) at fixed y (3-D), which march
+// along the slowest axis (z in 3-D, y in 2-D) over a segment of `mseg`
+// planes/rows.  The marching lane keeps the values of the previous and the
+// next plane in registers, so the stencil reads each vector from HBM about
+// once; x-neighbours come from adjacent lanes, y-neighbours in 3-D from L1/L2.
+// A block is four strips.  Every kernel of the solve walks a block table whose
+// entries name (instance, block-within-instance), so one launch serves one
+// grid or a whole batch of uneven grids; the table is ordered so that each
+// instance's consecutive blocks sit on one XCD (hardware assigns workgroup i
+// to XCD i mod 8), keeping plane-to-plane reuse inside one L2.
+#pragma once
+
+#include <stdint.h>
+
+namespace pi {
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kXcd = 8;
+constexpr uint32_t kValidBit = 1u << 31;
+constexpr int kStates = 20;      // per-direction counter states (3-D uses 0..18)
+constexpr int kSegCells = 65536; // gauge segment length (cells)
+#ifndef PI_STREAM_DEPTH
+#define PI_STREAM_DEPTH 4
+#endif
+constexpr int kStream = PI_STREAM_DEPTH;  // cells per lane in flight, streaming kernels
+
+// Per-direction code layout: 3-D 5 bits (state = 1 + n1 + 3 n2 + 9 far for a
+// face neighbour with data, 0 otherwise), 2-D 3 bits (state = 1 + n1 + 3 far).
+// n1, n2 count the face neighbour's laterals with data along the first and
+// second remaining axis (0..2); far is the neighbour's own far cell.
+__host__ __device__ inline int dir_bits(int ndim) { return ndim == 3 ? 5 : 3; }
+
+enum Dir { DE = 0, DW = 1, DN = 2, DS = 3, DF = 4, DB = 5 };
+
+struct BlockEnt {
+  int32_t inst;   // -1: padding entry, the block exits at once
+  int32_t lb;     // block index inside the instance
+};
+
+// Per-instance description, device resident (read-only inside kernels).
+struct Inst {
+  int32_t ndim;
+  int32_t nx, ny, nz;
+  int64_t ncell;
+  int32_t nxs;      // 64-wide strips along x
+  int32_t rows;     // strips stacked along y: ny in 3-D, 1 in 2-D
+  int32_t nm;       // length of the marching axis
+  int32_t mseg;     // marching segment length
+  int32_t nseg;
+  int32_t nblocks;  // blocks of this instance
+  int64_t nwaves;
+  int64_t sm;       // stride of the marching axis
+  int64_t srow;     // stride between stacked strips (nx in 3-D, 0 in 2-D)
+  int32_t part_base;// first slot of this instance in the partial-sum array
+  int32_t ncomp;    // connected groups of data cells
+  int32_t inner_iters; // inner Krylov iterations per outer step
+  double inv_nvalid;// 1 / data cells (gauge of a single group)
+  double a[6];      // per-direction face total / A_tot
+  double dsig[6];   // signed spacing Delta_j
+  double lut_np1[6][kStates];  // w_j^{n+1} by direction and state
+  double lut_n[6][kStates];    // w_j^{n}   by direction and state
+  const uint32_t *code;
+  // connected groups (all NULL when ncomp == 1): data cells sorted by group,
+  // cut into segments of at most kSegCells cells that never straddle groups
+  const int32_t *label;        // group of each cell
+  const double *comp_inv_count;// 1 / cells per group
+  double *comp_sum;            // per-group mean, filled by the gauge kernels
+  const int32_t *comp_order;   // data cells sorted by (group, index)
+  const int32_t *seg_begin;    // [nseg_g + 1] bounds into comp_order
+  const int32_t *comp_seg;     // [ncomp + 1] first segment of each group
+  double *seg_sum;             // [nseg_g] per-segment sums
+  int32_t nseg_g;
+  // workspace, typed by the plan's precision (T)
+  double *P[2];     // FP64 iterate, ping-pong
+  double *S64;      // source vector, kept in FP64 so that it sums to zero
+  void *S;          // optional copy of S in T (pi_source output), else NULL
+  void *res;
+  void *p[2];       // search direction, ping-pong
+  void *q;
+  void *d;          // correction accumulated by the inner solve
+  void *bs[4];      // BiCGStab: rhat, v, s, t
+  // per-solve user buffers
+  const void *g[3];
+  void *Pout;
+  const void *P0;
+  double tol;
+  int64_t max_iter;
+};
+
+// Mutable scalars of one instance.
+struct State {
+  double normS2;
+  double rr;        // CG: r.r of the current inner residual
+  double alpha, beta;
+  double rho, omega;// BiCGStab
+  double epsR, epsP;
+  double red[4];    // scratch for the last block's results
+  int64_t outer;
+  int64_t inner_total;
+  int32_t inner;    // inner iteration inside the current outer step
+  int32_t first;    // next search direction is the residual itself
+  int32_t pcur;     // current p buffer
+  int32_t Pcur;     // current P buffer
+  int32_t have_delta;
+  int32_t done;
+  int32_t status;   // pi_status
+  int32_t nonfinite;
+  uint32_t ticket;
+  int32_t pad;
+};
+
+}  // namespace pi

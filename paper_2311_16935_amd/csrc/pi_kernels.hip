@@ -1,0 +1,907 @@
+// HIP kernels of the solve (gfx950).
+//
+// All kernels are memory-bound stencils or streaming updates; no matrix
+// cores are involved.  Each kernel walks the block table described in
+// pi_common.h.  A kernel that reduces writes one FP64 partial per block and
+// nothing else crosses blocks inside a kernel: a small finalize kernel (one
+// block per instance) then sums the partials in a fixed order and updates
+// that instance's scalars.  The kernel boundary orders the two, so no fence
+// or atomic counter sits on the hot path, and results are bitwise
+// reproducible.
+//
+// Memory-level parallelism: a stencil wave fetches everything plane m+1
+// needs (operand, code word, source, y neighbours, strip-edge values) before
+// it computes plane m; streaming kernels load kStream cells per lane before
+// storing any of them.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "pi_common.h"
+#include "pi_kernels.h"
+
+namespace pi {
+
+// ---------------------------------------------------------------------------
+// work decomposition
+// ---------------------------------------------------------------------------
+struct Walk {
+  int64_t base;   // storage index of this lane's column at march position 0
+  int m0, m1;     // march range of this wave (uniform over the wave)
+  int x;          // x of this lane
+  int row;        // y of this wave's strip (3-D)
+  bool act;       // lane owns a cell column inside the grid
+};
+
+__device__ inline Walk make_walk(const Inst &in, int lb) {
+  Walk k{0, 0, 0, 0, 0, false};
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t)lb * kWavesPerBlock + wave;
+  if (w >= in.nwaves) return k;
+  int64_t xs, row, seg;
+  if (in.ndim == 3) {
+    // a block is four consecutive rows of one x strip
+    const int64_t nrg = (in.rows + 3) >> 2;
+    const int64_t rg = w >> 2;
+    xs = rg % in.nxs;
+    const int64_t t = rg / in.nxs;
+    row = (t % nrg) * 4 + (w & 3);
+    seg = t / nrg;
+    if (row >= in.rows) return k;
+  } else {
+    xs = w % in.nxs;
+    seg = w / in.nxs;
+    row = 0;
+  }
+  k.x = (int)(xs * kWave + lane);
+  k.m0 = (int)(seg * in.mseg);
+  k.m1 = min(k.m0 + in.mseg, in.nm);
+  k.act = k.x < in.nx;
+  k.row = (int)row;
+  k.base = (int64_t)k.x + row * in.srow;
+  return k;
+}
+
+__device__ inline int dstate(uint32_t code, int d, int bits) {
+  return (int)((code >> (bits * d)) & ((1u << bits) - 1u));
+}
+
+// One plane of a marching wave: everything the stencil needs at a cell,
+// fetched one plane ahead of its use.  vN/vS are the y neighbours (3-D only),
+// vEdge the x neighbour beyond the strip end (lane 0: west, lane 63: east).
+// Neighbours outside the grid read as 0; internal vectors hold 0 in masked
+// cells, and every neighbour value is used only through its counter state.
+template <typename V, typename A>
+struct Plane {
+  V v, vN, vS, vEdge;
+  A aux;
+  uint32_t code;
+};
+
+// March one wave along its segment.
+//   load(c)   stencil operand at an in-grid cell c
+//   aux(c)    extra per-cell input (the source in the outer step)
+//   body(c, plane, vW, vE, vPrev, vNext) -> Out   one cell; x neighbours come
+//             from adjacent lanes, march-axis neighbours from registers
+//   store(c, out)
+template <int ND, typename V, typename A, typename Out, typename Load, typename Aux, typename Body,
+          typename Store>
+__device__ inline void march(const Inst &in, const Walk &wk, Load load, Aux aux, Body body, Store store) {
+  if (wk.m1 <= wk.m0) return;  // uniform over the wave
+  const int lane = threadIdx.x & 63;
+  const bool hasN = ND == 3 && wk.row + 1 < in.ny, hasS = ND == 3 && wk.row > 0;
+  const bool edgeW = lane == 0 && wk.x > 0, edgeE = lane == kWave - 1 && wk.x + 1 < in.nx;
+  const int64_t snx = in.nx;
+  auto fetch = [&](int64_t c, Plane<V, A> &pl) {
+    pl.v = load(c);
+    pl.code = in.code[c];
+    pl.aux = aux(c);
+    if (ND == 3) {
+      pl.vN = hasN ? load(c + snx) : V(0);
+      pl.vS = hasS ? load(c - snx) : V(0);
+    }
+    pl.vEdge = edgeW ? load(c - 1) : edgeE ? load(c + 1) : V(0);
+  };
+  int64_t c = wk.base + (int64_t)wk.m0 * in.sm;
+  V prev = (wk.act && wk.m0 > 0) ? load(c - in.sm) : V(0);
+  Plane<V, A> cur{}, nxt{};
+  if (wk.act) fetch(c, cur);
+  for (int m = wk.m0; m < wk.m1; ++m, c += in.sm) {
+    nxt.v = V(0);
+    if (wk.act && m + 1 < in.nm) {
+      if (m + 1 < wk.m1)
+        fetch(c + in.sm, nxt);
+      else
+        nxt.v = load(c + in.sm);  // last plane of the segment: its successor is only a neighbour
+    }
+    V vW = __shfl_up(cur.v, 1, kWave);
+    V vE = __shfl_down(cur.v, 1, kWave);
+    if (lane == 0) vW = cur.vEdge;
+    if (lane == kWave - 1) vE = cur.vEdge;
+    if (wk.act) store(c, body(c, cur, vW, vE, prev, nxt.v));
+    prev = cur.v;
+    cur = nxt;
+  }
+}
+
+// Stream over the cells of one wave's segment, kStream cells per lane at a
+// time: f.load(c, u) for all u first, then f.apply(c, u).
+template <typename F>
+__device__ inline void stream(const Inst &in, const Walk &wk, F &f) {
+  if (!wk.act) return;
+  for (int m = wk.m0; m < wk.m1; m += kStream) {
+    const int64_t cm = wk.base + (int64_t)m * in.sm;
+#pragma unroll
+    for (int u = 0; u < kStream; ++u)
+      if (m + u < wk.m1) f.load(cm + (int64_t)u * in.sm, u);
+#pragma unroll
+    for (int u = 0; u < kStream; ++u)
+      if (m + u < wk.m1) f.apply(cm + (int64_t)u * in.sm, u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ inline void block_sum(double (&v)[K], double *lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, kWave);
+  }
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[wave * K + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = ((lds[k] + lds[K + k]) + lds[2 * K + k]) + lds[3 * K + k];
+  }
+}
+
+// Write this block's K partial sums into its slot (4 doubles per block).
+template <int K>
+__device__ inline void publish(const Inst &in, double *part, int lb, double (&v)[K]) {
+  __shared__ double lds[kWavesPerBlock * 4];
+  block_sum<K>(v, lds);
+  if (threadIdx.x == 0) {
+    double *slot = part + ((int64_t)in.part_base + lb) * 4;
+#pragma unroll
+    for (int k = 0; k < K; ++k) slot[k] = v[k];
+  }
+}
+
+template <typename T>
+__device__ inline void load_lut(const double (*src)[kStates], T (*dst)[kStates]) {
+  for (int i = threadIdx.x; i < 6 * kStates; i += kBlock) dst[i / kStates][i % kStates] = (T)src[i / kStates][i % kStates];
+  __syncthreads();
+}
+
+#define PI_PROLOGUE                                   \
+  const BlockEnt e = tab[blockIdx.x];                 \
+  if (e.inst < 0) return;                             \
+  const Inst &in = insts[e.inst];                     \
+  State *st = sts + e.inst;
+
+// Skip conditions, evaluated identically by a kernel and by its finalize.
+__device__ inline bool skip_outer(const State *st) { return st->done != 0; }
+__device__ inline bool skip_inner(const Inst &in, const State *st) {
+  return st->done != 0 || st->inner >= in.inner_iters;
+}
+
+// ---------------------------------------------------------------------------
+// set-up: P^0 and the source vector
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init(const BlockEnt *tab, const Inst *insts, State *sts, double *part,
+                                                 int warm) {
+  PI_PROLOGUE
+  const Walk wk = make_walk(in, e.lb);
+  const T *P0 = (const T *)in.P0;
+  double *P = in.P[0];
+  int bad = 0;
+  if (wk.act) {
+    int64_t c = wk.base + (int64_t)wk.m0 * in.sm;
+    for (int m = wk.m0; m < wk.m1; ++m, c += in.sm) {
+      double v = 0.0;
+      if (warm && (in.code[c] & kValidBit)) {
+        v = (double)P0[c];
+        if (!isfinite(v)) {
+          bad = 1;
+          v = 0.0;
+        }
+      }
+      P[c] = v;
+    }
+  }
+  if (bad) atomicOr(&st->nonfinite, 1);
+}
+
+// S_C = - sum_j Delta_j (w_j^{n+1} + w_j^n) (f_j(J) + f_j(C)) / 2 over face
+// neighbours J holding data (Eq. ExplicitEqn_FaceCrossing).  For such J the
+// two counters add up to the face total (Eq. AE_Interior and the 3-D face
+// integral), so w_j^{n+1} + w_j^n = a_j.  FP64 arithmetic and FP64 storage:
+// the face terms cancel in pairs, so S sums to zero over every connected
+// group; a float copy would not, and its constant part would put a floor of
+// about 6e-8 / sqrt(cells) under the reachable residual.
+template <typename T, int ND>
+__global__ __launch_bounds__(kBlock) void k_source(const BlockEnt *tab, const Inst *insts, State *sts, double *part) {
+  PI_PROLOGUE
+  const Walk wk = make_walk(in, e.lb);
+  const T *g[3] = {(const T *)in.g[0], (const T *)in.g[1], (const T *)in.g[2]};
+  T *S = (T *)in.S;
+  double *S64 = in.S64;
+  const int bits = dir_bits(ND);
+  const int64_t off[6] = {1, -1, (int64_t)in.nx, -(int64_t)in.nx, ND == 3 ? (int64_t)in.nx * in.ny : 0,
+                          ND == 3 ? -(int64_t)in.nx * in.ny : 0};
+  double acc[1] = {0.0};
+  int bad = 0;
+  if (wk.act) {
+    int64_t c = wk.base + (int64_t)wk.m0 * in.sm;
+    for (int m = wk.m0; m < wk.m1; ++m, c += in.sm) {
+      const uint32_t cd = in.code[c];
+      double s = 0.0;
+      if (cd & kValidBit) {
+        double own[3];
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+          own[a] = (double)g[a][c];
+          if (!isfinite(own[a])) bad = 1;
+        }
+#pragma unroll
+        for (int d = 0; d < 2 * ND; ++d) {
+          if (dstate(cd, d, bits)) {
+            const int a = d >> 1;
+            const double nb = (double)g[a][c + off[d]];
+            s -= in.dsig[d] * in.a[d] * 0.5 * (nb + own[a]);
+          }
+        }
+      }
+      S64[c] = s;
+      if (S) S[c] = (T)s;
+      acc[0] += s * s;
+    }
+  }
+  if (bad) atomicOr(&st->nonfinite, 1);
+  publish<1>(in, part, e.lb, acc);
+}
+
+// ---------------------------------------------------------------------------
+// outer step: P^{n+1} = P^n + delta, r = S - (M - N) P^{n+1}, eps_R
+// ---------------------------------------------------------------------------
+// (M - N) is applied as sum_j a_j (P_C - P_J) over face neighbours holding
+// data: its off-diagonal entries are -(w_j^{n+1} + w_j^n) = -a_j and, since
+// all counters of a data cell add up to A_tot, its diagonal 1 - w_C^n equals
+// sum_j a_j.
+template <typename T, int ND>
+__global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Inst *insts, State *sts, double *part) {
+  PI_PROLOGUE
+  if (skip_outer(st)) return;
+  const Walk wk = make_walk(in, e.lb);
+  const int cur = st->Pcur;
+  const bool hd = st->have_delta != 0;
+  const double *Pold = in.P[cur];
+  double *Pnew = in.P[cur ^ 1];
+  const T *dl = (const T *)in.d;
+  const double *S = in.S64;
+  T *res = (T *)in.res;
+  const int bits = dir_bits(ND);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  struct Out {
+    double p, r;
+  };
+  auto load = [&](int64_t c) -> double { return hd ? Pold[c] + (double)dl[c] : Pold[c]; };
+  struct Aux {
+    double S, d;
+  };
+  auto aux = [&](int64_t c) -> Aux { return Aux{S[c], hd ? (double)dl[c] : 0.0}; };
+  auto body = [&](int64_t c, const Plane<double, Aux> &pl, double vW, double vE, double vP,
+                  double vN) -> Out {
+    const uint32_t cd = pl.code;
+    if (!(cd & kValidBit)) return Out{0.0, 0.0};
+    const double vC = pl.v;
+    double Lp = 0.0;
+    if (dstate(cd, DE, bits)) Lp += in.a[DE] * (vC - vE);
+    if (dstate(cd, DW, bits)) Lp += in.a[DW] * (vC - vW);
+    if (ND == 3) {
+      if (dstate(cd, DN, bits)) Lp += in.a[DN] * (vC - pl.vN);
+      if (dstate(cd, DS, bits)) Lp += in.a[DS] * (vC - pl.vS);
+      if (dstate(cd, DF, bits)) Lp += in.a[DF] * (vC - vN);
+      if (dstate(cd, DB, bits)) Lp += in.a[DB] * (vC - vP);
+    } else {
+      if (dstate(cd, DN, bits)) Lp += in.a[DN] * (vC - vN);
+      if (dstate(cd, DS, bits)) Lp += in.a[DS] * (vC - vP);
+    }
+    const double r = pl.aux.S - Lp;
+    const double rt = (double)(T)r;
+    acc[0] += r * r;
+    acc[1] += rt * rt;
+    acc[2] += pl.aux.d * pl.aux.d;
+    acc[3] += vC * vC;
+    return Out{vC, r};
+  };
+  auto store = [&](int64_t c, const Out &o) {
+    Pnew[c] = o.p;
+    res[c] = (T)o.r;
+  };
+  march<ND, double, Aux, Out>(in, wk, load, aux, body, store);
+  publish<4>(in, part, e.lb, acc);
+}
+
+// ---------------------------------------------------------------------------
+// inner conjugate gradient on M delta = r
+// ---------------------------------------------------------------------------
+// p <- r + beta p (or p <- r on the first iteration), q <- M p, p.q
+template <typename T, int ND>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                    double *part) {
+  PI_PROLOGUE
+  if (skip_inner(in, st)) return;
+  __shared__ T lut[6][kStates];
+  load_lut<T>(in.lut_np1, lut);
+  const Walk wk = make_walk(in, e.lb);
+  const bool first = st->first != 0;
+  const T beta = (T)st->beta;
+  const int pc = st->pcur;
+  const T *pold = (const T *)in.p[pc];
+  T *pnew = (T *)in.p[pc ^ 1];
+  const T *res = (const T *)in.res;
+  T *q = (T *)in.q;
+  const int bits = dir_bits(ND);
+  double acc[1] = {0.0};
+  struct Out {
+    T p, q;
+  };
+  auto load = [&](int64_t c) -> T { return first ? res[c] : res[c] + beta * pold[c]; };
+  auto body = [&](int64_t c, const Plane<T, int> &pl, T vW, T vE, T vP, T vN) -> Out {
+    const uint32_t cd = pl.code;
+    const T vC = pl.v;
+    if (!(cd & kValidBit)) return Out{T(0), T(0)};
+    T s = vC;
+    int t;
+    if ((t = dstate(cd, DE, bits))) s -= lut[DE][t] * vE;
+    if ((t = dstate(cd, DW, bits))) s -= lut[DW][t] * vW;
+    if (ND == 3) {
+      if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * pl.vN;
+      if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * pl.vS;
+      if ((t = dstate(cd, DF, bits))) s -= lut[DF][t] * vN;
+      if ((t = dstate(cd, DB, bits))) s -= lut[DB][t] * vP;
+    } else {
+      if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * vN;
+      if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * vP;
+    }
+    acc[0] += (double)vC * (double)s;
+    return Out{vC, s};
+  };
+  auto store = [&](int64_t c, const Out &o) {
+    pnew[c] = o.p;
+    q[c] = o.q;
+  };
+  march<ND, T, int, Out>(in, wk, load, [](int64_t) { return 0; }, body, store);
+  publish<1>(in, part, e.lb, acc);
+}
+
+// delta <- delta + alpha p (delta <- alpha p on the first iteration),
+// r <- r - alpha q, r.r
+template <typename T>
+struct CgUpdate {
+  const T *p, *q;
+  T *res, *d;
+  T alpha;
+  bool first;
+  double acc;
+  T pv[kStream], qv[kStream], rv[kStream], dv[kStream];
+  __device__ void load(int64_t c, int u) {
+    pv[u] = p[c];
+    qv[u] = q[c];
+    rv[u] = res[c];
+    dv[u] = first ? T(0) : d[c];
+  }
+  __device__ void apply(int64_t c, int u) {
+    const T r = rv[u] - alpha * qv[u];
+    d[c] = dv[u] + alpha * pv[u];
+    res[c] = r;
+    acc += (double)r * (double)r;
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                      double *part) {
+  PI_PROLOGUE
+  if (skip_inner(in, st)) return;
+  const Walk wk = make_walk(in, e.lb);
+  CgUpdate<T> f;
+  f.p = (const T *)in.p[st->pcur];
+  f.q = (const T *)in.q;
+  f.res = (T *)in.res;
+  f.d = (T *)in.d;
+  f.alpha = (T)st->alpha;
+  f.first = st->inner == 0;
+  f.acc = 0.0;
+  stream(in, wk, f);
+  double acc[1] = {f.acc};
+  publish<1>(in, part, e.lb, acc);
+}
+
+// ---------------------------------------------------------------------------
+// inner BiCGStab on M delta = r (shadow residual = the outer residual)
+// ---------------------------------------------------------------------------
+// phase 1: p <- r + beta (p - omega v) (p <- r first), v' <- M p (into q), rhat.v'
+template <typename T, int ND>
+__global__ __launch_bounds__(kBlock) void k_bicg_spmv_p(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                        double *part) {
+  PI_PROLOGUE
+  if (skip_inner(in, st)) return;
+  __shared__ T lut[6][kStates];
+  load_lut<T>(in.lut_np1, lut);
+  const Walk wk = make_walk(in, e.lb);
+  const bool first = st->first != 0;
+  const T beta = (T)st->beta, omega = (T)st->omega;
+  const int pc = st->pcur;
+  const T *pold = (const T *)in.p[pc];
+  T *pnew = (T *)in.p[pc ^ 1];
+  const T *res = (const T *)in.res;
+  const T *v = (const T *)in.bs[1];
+  const T *rhat = (const T *)in.bs[0];
+  T *vnew = (T *)in.q;
+  const int bits = dir_bits(ND);
+  double acc[1] = {0.0};
+  struct Out {
+    T p, v;
+  };
+  auto load = [&](int64_t c) -> T { return first ? res[c] : res[c] + beta * (pold[c] - omega * v[c]); };
+  auto body = [&](int64_t c, const Plane<T, int> &pl, T vW, T vE, T vP, T vN) -> Out {
+    const uint32_t cd = pl.code;
+    const T vC = pl.v;
+    if (!(cd & kValidBit)) return Out{T(0), T(0)};
+    T s = vC;
+    int t;
+    if ((t = dstate(cd, DE, bits))) s -= lut[DE][t] * vE;
+    if ((t = dstate(cd, DW, bits))) s -= lut[DW][t] * vW;
+    if (ND == 3) {
+      if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * pl.vN;
+      if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * pl.vS;
+      if ((t = dstate(cd, DF, bits))) s -= lut[DF][t] * vN;
+      if ((t = dstate(cd, DB, bits))) s -= lut[DB][t] * vP;
+    } else {
+      if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * vN;
+      if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * vP;
+    }
+    acc[0] += (double)rhat[c] * (double)s;
+    return Out{vC, s};
+  };
+  auto store = [&](int64_t c, const Out &o) {
+    pnew[c] = o.p;
+    vnew[c] = o.v;
+  };
+  march<ND, T, int, Out>(in, wk, load, [](int64_t) { return 0; }, body, store);
+  publish<1>(in, part, e.lb, acc);
+}
+
+// phase 2: v <- v', s <- r - alpha v, t <- M s, t.s and t.t
+template <typename T, int ND>
+__global__ __launch_bounds__(kBlock) void k_bicg_spmv_s(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                        double *part) {
+  PI_PROLOGUE
+  if (skip_inner(in, st)) return;
+  __shared__ T lut[6][kStates];
+  load_lut<T>(in.lut_np1, lut);
+  const Walk wk = make_walk(in, e.lb);
+  const T alpha = (T)st->alpha;
+  const T *res = (const T *)in.res;
+  const T *vnew = (const T *)in.q;
+  T *v = (T *)in.bs[1];
+  T *s_out = (T *)in.bs[2];
+  T *t_out = (T *)in.bs[3];
+  const int bits = dir_bits(ND);
+  double acc[2] = {0.0, 0.0};
+  struct Out {
+    T v, s, t;
+  };
+  auto load = [&](int64_t c) -> T { return res[c] - alpha * vnew[c]; };
+  auto body = [&](int64_t c, const Plane<T, int> &pl, T vW, T vE, T vP, T vN) -> Out {
+    const uint32_t cd = pl.code;
+    const T vC = pl.v;
+    const T vv = vnew[c];
+    if (!(cd & kValidBit)) return Out{vv, T(0), T(0)};
+    T s = vC;
+    int t;
+    if ((t = dstate(cd, DE, bits))) s -= lut[DE][t] * vE;
+    if ((t = dstate(cd, DW, bits))) s -= lut[DW][t] * vW;
+    if (ND == 3) {
+      if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * pl.vN;
+      if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * pl.vS;
+      if ((t = dstate(cd, DF, bits))) s -= lut[DF][t] * vN;
+      if ((t = dstate(cd, DB, bits))) s -= lut[DB][t] * vP;
+    } else {
+      if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * vN;
+      if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * vP;
+    }
+    acc[0] += (double)s * (double)vC;
+    acc[1] += (double)s * (double)s;
+    return Out{vv, vC, s};
+  };
+  auto store = [&](int64_t c, const Out &o) {
+    v[c] = o.v;
+    s_out[c] = o.s;
+    t_out[c] = o.t;
+  };
+  march<ND, T, int, Out>(in, wk, load, [](int64_t) { return 0; }, body, store);
+  publish<2>(in, part, e.lb, acc);
+}
+
+// phase 3: delta <- delta + alpha p + omega s, r <- s - omega t, rhat.r
+template <typename T>
+struct BicgUpdate {
+  const T *p, *s, *t, *rhat;
+  T *res, *d;
+  T alpha, omega;
+  bool first;
+  double acc;
+  T pv[kStream], sv[kStream], tv[kStream], hv[kStream], dv[kStream];
+  __device__ void load(int64_t c, int u) {
+    pv[u] = p[c];
+    sv[u] = s[c];
+    tv[u] = t[c];
+    hv[u] = rhat[c];
+    dv[u] = first ? T(0) : d[c];
+  }
+  __device__ void apply(int64_t c, int u) {
+    d[c] = dv[u] + (alpha * pv[u] + omega * sv[u]);
+    const T r = sv[u] - omega * tv[u];
+    res[c] = r;
+    acc += (double)hv[u] * (double)r;
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bicg_update(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                        double *part) {
+  PI_PROLOGUE
+  if (skip_inner(in, st)) return;
+  const Walk wk = make_walk(in, e.lb);
+  BicgUpdate<T> f;
+  f.p = (const T *)in.p[st->pcur];
+  f.s = (const T *)in.bs[2];
+  f.t = (const T *)in.bs[3];
+  f.rhat = (const T *)in.bs[0];
+  f.res = (T *)in.res;
+  f.d = (T *)in.d;
+  f.alpha = (T)st->alpha;
+  f.omega = (T)st->omega;
+  f.first = st->inner == 0;
+  f.acc = 0.0;
+  stream(in, wk, f);
+  double acc[1] = {f.acc};
+  publish<1>(in, part, e.lb, acc);
+}
+
+// copy of the outer residual used as BiCGStab's shadow vector
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy_res(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                     double *part) {
+  PI_PROLOGUE
+  if (skip_outer(st)) return;
+  const Walk wk = make_walk(in, e.lb);
+  const T *res = (const T *)in.res;
+  T *rhat = (T *)in.bs[0];
+  if (wk.act) {
+    int64_t c = wk.base + (int64_t)wk.m0 * in.sm;
+    for (int m = wk.m0; m < wk.m1; ++m, c += in.sm) rhat[c] = res[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gauge: remove the mean of P over every connected group of data cells
+// ---------------------------------------------------------------------------
+// Single group: fixed-order block partials.  Several groups: one block per
+// segment of the group-sorted cell list (fixed order inside), then one thread
+// per group sums its segments in order -- deterministic in both cases.
+__global__ __launch_bounds__(kBlock) void k_gauge_sum(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                      double *part) {
+  PI_PROLOGUE
+  const double *P = in.P[st->Pcur];
+  if (in.ncomp > 1) {
+    __shared__ double lds[kWavesPerBlock * 4];
+    for (int sg = e.lb; sg < in.nseg_g; sg += in.nblocks) {
+      double v[1] = {0.0};
+      for (int i = in.seg_begin[sg] + threadIdx.x; i < in.seg_begin[sg + 1]; i += kBlock) v[0] += P[in.comp_order[i]];
+      block_sum<1>(v, lds);
+      if (threadIdx.x == 0) in.seg_sum[sg] = v[0];
+    }
+    return;
+  }
+  const Walk wk = make_walk(in, e.lb);
+  double acc[1] = {0.0};
+  if (wk.act) {
+    int64_t c = wk.base + (int64_t)wk.m0 * in.sm;
+    for (int m = wk.m0; m < wk.m1; ++m, c += in.sm)
+      if (in.code[c] & kValidBit) acc[0] += P[c];
+  }
+  publish<1>(in, part, e.lb, acc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gauge_groups(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                         double *part) {
+  PI_PROLOGUE
+  if (in.ncomp <= 1) return;
+  for (int k = e.lb * kBlock + threadIdx.x; k < in.ncomp; k += in.nblocks * kBlock) {
+    double s = 0.0;
+    for (int sg = in.comp_seg[k]; sg < in.comp_seg[k + 1]; ++sg) s += in.seg_sum[sg];
+    in.comp_sum[k] = s * in.comp_inv_count[k];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gauge_apply(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                        double *part) {
+  PI_PROLOGUE
+  const Walk wk = make_walk(in, e.lb);
+  const double *P = in.P[st->Pcur];
+  T *out = (T *)in.Pout;
+  const bool zero = st->normS2 == 0.0;
+  const double mean1 = st->red[0] * in.inv_nvalid;
+  if (wk.act) {
+    int64_t c = wk.base + (int64_t)wk.m0 * in.sm;
+    for (int m = wk.m0; m < wk.m1; ++m, c += in.sm) {
+      T v;
+      if (in.code[c] & kValidBit) {
+        if (zero) {
+          v = T(0);
+        } else if (in.ncomp > 1) {
+          v = (T)(P[c] - in.comp_sum[in.label[c]]);
+        } else {
+          v = (T)(P[c] - mean1);
+        }
+      } else {
+        v = (T)NAN;
+      }
+      out[c] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// finalize: one block per instance sums the partials of the kernel that just
+// ran (fixed order) and updates the instance's scalars
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *sts, const double *part, int kind) {
+  const Inst &in = insts[blockIdx.x];
+  State *st = sts + blockIdx.x;
+  switch (kind) {
+    case K_SOURCE: break;
+    case K_OUTER:
+    case K_COPY_RES:
+      if (skip_outer(st)) return;
+      break;
+    case K_GAUGE_SUM:
+      if (in.ncomp > 1) return;
+      break;
+    default:
+      if (skip_inner(in, st)) return;
+  }
+  __shared__ double lds[kWavesPerBlock * 4];
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < in.nblocks; i += kBlock) {
+    const double *slot = part + ((int64_t)in.part_base + i) * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[k] += slot[k];
+  }
+  block_sum<4>(s, lds);
+  if (threadIdx.x != 0) return;
+  switch (kind) {
+    case K_SOURCE:
+      st->normS2 = s[0];
+      if (st->nonfinite) {
+        st->done = 1;
+        st->status = 3;  // PI_ERR_NONFINITE
+      }
+      break;
+    case K_OUTER: {
+      const bool hd = st->have_delta != 0;
+      const double epsR = st->normS2 > 0.0 ? sqrt(s[0] / st->normS2) : 0.0;
+      st->epsR = epsR;
+      if (hd) st->epsP = s[3] > 0.0 ? sqrt(s[2] / s[3]) : 0.0;
+      st->Pcur ^= 1;
+      if (!isfinite(epsR)) {
+        st->done = 1;
+        st->status = 5;  // PI_ERR_DIVERGED
+      } else if (epsR <= in.tol) {
+        st->done = 1;
+        st->status = 0;
+      } else if (st->outer >= in.max_iter) {
+        st->done = 1;
+        st->status = 4;  // PI_ERR_NOT_CONVERGED
+      } else {
+        st->outer += 1;
+        st->rr = s[1];
+        st->inner = 0;
+        st->first = 1;
+        st->have_delta = 1;
+        // BiCGStab restarts with the new residual as its shadow vector
+        st->rho = s[1];
+        st->alpha = 1.0;
+        st->omega = 1.0;
+      }
+      break;
+    }
+    case K_CG_SPMV:
+      st->alpha = s[0] != 0.0 ? st->rr / s[0] : 0.0;
+      st->pcur ^= 1;
+      st->first = 0;
+      break;
+    case K_CG_UPDATE:
+      st->beta = st->rr != 0.0 ? s[0] / st->rr : 0.0;
+      st->rr = s[0];
+      st->inner += 1;
+      st->inner_total += 1;
+      break;
+    case K_BICG_P:
+      st->alpha = s[0] != 0.0 ? st->rho / s[0] : 0.0;
+      st->pcur ^= 1;
+      st->first = 0;
+      break;
+    case K_BICG_S:
+      st->omega = s[1] != 0.0 ? s[0] / s[1] : 0.0;
+      break;
+    case K_BICG_UPDATE: {
+      const double rho_new = s[0];
+      st->beta = (st->rho != 0.0 && st->omega != 0.0) ? (rho_new / st->rho) * (st->alpha / st->omega) : 0.0;
+      st->rho = rho_new;
+      st->inner += 1;
+      st->inner_total += 1;
+      break;
+    }
+    case K_GAUGE_SUM:
+      st->red[0] = s[0];
+      break;
+    default: break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plain operator applies (pi_apply): y = M x, N x or (M - N) x
+// ---------------------------------------------------------------------------
+template <typename T, int ND>
+__global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Inst *insts, State *sts, double *part,
+                                                  int op, const T *x, T *y) {
+  PI_PROLOGUE
+  __shared__ T lut_a[6][kStates];
+  __shared__ T lut_b[6][kStates];
+  load_lut<T>(in.lut_np1, lut_a);
+  load_lut<T>(in.lut_n, lut_b);
+  const Walk wk = make_walk(in, e.lb);
+  const int bits = dir_bits(ND);
+  auto load = [&](int64_t c) -> T { return x[c]; };
+  auto body = [&](int64_t c, const Plane<T, int> &pl, T vW, T vE, T vP, T vN) -> T {
+    const uint32_t cd = pl.code;
+    const T vC = pl.v;
+    if (!(cd & kValidBit)) return T(0);
+    T nb[6];
+    nb[DE] = vE;
+    nb[DW] = vW;
+    if (ND == 3) {
+      nb[DN] = pl.vN;
+      nb[DS] = pl.vS;
+      nb[DF] = vN;
+      nb[DB] = vP;
+    } else {
+      nb[DN] = vN;
+      nb[DS] = vP;
+    }
+    T s;
+    if (op == 0) {  // M = I - W^{n+1}
+      s = vC;
+      for (int d = 0; d < 2 * ND; ++d) {
+        const int t = dstate(cd, d, bits);
+        if (t) s -= lut_a[d][t] * nb[d];
+      }
+    } else if (op == 1) {  // N = W^n with diagonal w_C^n
+      T wc = T(1);
+      s = T(0);
+      for (int d = 0; d < 2 * ND; ++d) {
+        const int t = dstate(cd, d, bits);
+        if (t) {
+          s += lut_b[d][t] * nb[d];
+          wc -= (T)in.a[d];
+        }
+      }
+      s += wc * vC;
+    } else {  // M - N
+      s = T(0);
+      for (int d = 0; d < 2 * ND; ++d) {
+        const int t = dstate(cd, d, bits);
+        if (t) s += (T)in.a[d] * (vC - nb[d]);
+      }
+    }
+    return s;
+  };
+  auto store = [&](int64_t c, const T &v) { y[c] = v; };
+  march<ND, T, int, T>(in, wk, load, [](int64_t) { return 0; }, body, store);
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+#define PI_ARGS tab, insts, sts, part
+
+template <typename T>
+static hipError_t launch_t(KernelId k, int ndim, const LaunchArgs &la) {
+  const dim3 grid(la.nblocks), block(kBlock);
+  const BlockEnt *tab = la.tab;
+  const Inst *insts = la.insts;
+  State *sts = la.sts;
+  double *part = la.part;
+  hipStream_t s = la.stream;
+  switch (k) {
+    case K_INIT: k_init<T><<<grid, block, 0, s>>>(PI_ARGS, la.iarg); break;
+    case K_SOURCE:
+      if (ndim == 3) k_source<T, 3><<<grid, block, 0, s>>>(PI_ARGS);
+      else k_source<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
+      break;
+    case K_OUTER:
+      if (ndim == 3) k_outer<T, 3><<<grid, block, 0, s>>>(PI_ARGS);
+      else k_outer<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
+      break;
+    case K_CG_SPMV:
+      if (ndim == 3) k_cg_spmv<T, 3><<<grid, block, 0, s>>>(PI_ARGS);
+      else k_cg_spmv<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
+      break;
+    case K_CG_UPDATE: k_cg_update<T><<<grid, block, 0, s>>>(PI_ARGS); break;
+    case K_BICG_P:
+      if (ndim == 3) k_bicg_spmv_p<T, 3><<<grid, block, 0, s>>>(PI_ARGS);
+      else k_bicg_spmv_p<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
+      break;
+    case K_BICG_S:
+      if (ndim == 3) k_bicg_spmv_s<T, 3><<<grid, block, 0, s>>>(PI_ARGS);
+      else k_bicg_spmv_s<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
+      break;
+    case K_BICG_UPDATE: k_bicg_update<T><<<grid, block, 0, s>>>(PI_ARGS); break;
+    case K_COPY_RES: k_copy_res<T><<<grid, block, 0, s>>>(PI_ARGS); break;
+    case K_GAUGE_GROUPS: k_gauge_groups<<<grid, block, 0, s>>>(PI_ARGS); break;
+    case K_GAUGE_SUM: k_gauge_sum<<<grid, block, 0, s>>>(PI_ARGS); break;
+    case K_GAUGE_APPLY: k_gauge_apply<T><<<grid, block, 0, s>>>(PI_ARGS); break;
+    case K_APPLY:
+      if (ndim == 3)
+        k_apply<T, 3><<<grid, block, 0, s>>>(PI_ARGS, la.iarg, (const T *)la.x, (T *)la.y);
+      else
+        k_apply<T, 2><<<grid, block, 0, s>>>(PI_ARGS, la.iarg, (const T *)la.x, (T *)la.y);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch(KernelId k, bool fp64, int ndim, const LaunchArgs &la) {
+  if (la.nblocks <= 0) return hipSuccess;
+  return fp64 ? launch_t<double>(k, ndim, la) : launch_t<float>(k, ndim, la);
+}
+
+bool reduces(KernelId k) {
+  switch (k) {
+    case K_SOURCE:
+    case K_OUTER:
+    case K_CG_SPMV:
+    case K_CG_UPDATE:
+    case K_BICG_P:
+    case K_BICG_S:
+    case K_BICG_UPDATE:
+    case K_GAUGE_SUM: return true;
+    default: return false;
+  }
+}
+
+hipError_t launch_finalize(KernelId k, const Inst *insts, State *sts, const double *part, int count,
+                           hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  k_finalize<<<dim3(count), dim3(kBlock), 0, s>>>(insts, sts, part, (int)k);
+  return hipGetLastError();
+}
+
+}  // namespace pi

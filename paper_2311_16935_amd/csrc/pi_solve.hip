@@ -1,0 +1,428 @@
+// Solve driver: Algorithm 1 on the device, one or many grids at a time.
+//
+// One outer step is a fixed sequence of launches -- the outer residual and
+// update, then `inner` Krylov iterations -- over the block table.  All
+// scalars (alpha, beta, eps_R, convergence flags) live in device State
+// records, so the sequence is captured once as a HIP graph (several outer
+// steps unrolled) and replayed; the host only polls the done flags, and it
+// overlaps each poll with the next replays.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <vector>
+
+#include "pi_kernels.h"
+#include "pi_plan.h"
+
+using namespace pi;
+
+namespace {
+
+constexpr int kUnroll = 8;  // outer steps per graph replay
+
+struct Group {               // instances of one dimensionality
+  BlockEnt *tab = nullptr;   // device
+  int ntab = 0;
+};
+
+struct Launcher {
+  bool fp64 = false;
+  Inst *insts = nullptr;
+  State *sts = nullptr;
+  double *part = nullptr;
+  int count = 0;             // instances
+  Group grp[2];              // [0] = 2-D, [1] = 3-D
+
+  // the kernel over every instance, then (if it reduces) its finalize
+  hipError_t go(KernelId k, hipStream_t s, int iarg = 0, const void *x = nullptr, void *y = nullptr,
+                bool finalize = true) const {
+    for (int g = 0; g < 2; ++g) {
+      if (grp[g].ntab <= 0) continue;
+      LaunchArgs la{grp[g].tab, insts, sts, part, grp[g].ntab, s, iarg, x, y};
+      hipError_t e = launch(k, fp64, g == 0 ? 2 : 3, la);
+      if (e != hipSuccess) return e;
+    }
+    if (finalize && reduces(k)) return launch_finalize(k, insts, sts, part, count, s);
+    return hipSuccess;
+  }
+
+  hipError_t outer_steps(hipStream_t s, int unroll, int inner, bool bicg) const {
+    for (int u = 0; u < unroll; ++u) {
+      hipError_t e = go(K_OUTER, s);
+      if (e != hipSuccess) return e;
+      if (bicg && (e = go(K_COPY_RES, s)) != hipSuccess) return e;
+      for (int i = 0; i < inner; ++i) {
+        if (bicg) {
+          if ((e = go(K_BICG_P, s)) != hipSuccess) return e;
+          if ((e = go(K_BICG_S, s)) != hipSuccess) return e;
+          if ((e = go(K_BICG_UPDATE, s)) != hipSuccess) return e;
+        } else {
+          if ((e = go(K_CG_SPMV, s)) != hipSuccess) return e;
+          if ((e = go(K_CG_UPDATE, s)) != hipSuccess) return e;
+        }
+      }
+    }
+    return hipSuccess;
+  }
+};
+
+hipError_t capture(const Launcher &L, hipStream_t cap, int inner, bool bicg, hipGraphExec_t *exec) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t e2 = L.outer_steps(cap, kUnroll, inner, bicg);
+  e = hipStreamEndCapture(cap, &g);
+  if (e2 != hipSuccess) e = e2;
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+  }
+  e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e;
+}
+
+State fresh_state() {
+  State s;
+  memset(&s, 0, sizeof(s));
+  s.first = 1;
+  s.alpha = 1.0;
+  s.omega = 1.0;
+  return s;
+}
+
+// Replay the outer-step graph until every instance reports done.  `hstate`
+// is a pinned buffer of 2 * count records.
+pi_status iterate(hipGraphExec_t exec, hipStream_t stream, State *dstate, State *hstate, int64_t count,
+                  int64_t max_iter) {
+  hipEvent_t ev[2];
+  if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess) return PI_ERR_DEVICE;
+  if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return PI_ERR_DEVICE;
+  }
+  // every replay advances each unfinished instance by kUnroll outer steps
+  const int64_t bound = max_iter / kUnroll + 4;
+  int64_t launched = 0;
+  int replays = 1;
+  int cur = 0;
+  bool pending = false;
+  pi_status rc = PI_ERR_DEVICE;
+  const size_t bytes = (size_t)count * sizeof(State);
+  for (;;) {
+    const int r = (int)std::min<int64_t>(replays, bound - launched);
+    for (int i = 0; i < r; ++i)
+      if (hipGraphLaunch(exec, stream) != hipSuccess) goto out;
+    launched += r;
+    if (hipMemcpyAsync(hstate + cur * count, dstate, bytes, hipMemcpyDeviceToHost, stream) != hipSuccess) goto out;
+    if (hipEventRecord(ev[cur], stream) != hipSuccess) goto out;
+    if (pending) {
+      // check the previous snapshot while the latest replays run
+      const int prev = cur ^ 1;
+      if (hipEventSynchronize(ev[prev]) != hipSuccess) goto out;
+      bool all = true;
+      for (int64_t i = 0; i < count && all; ++i) all = hstate[prev * count + i].done != 0;
+      if (all) {
+        rc = PI_OK;
+        break;
+      }
+    }
+    pending = true;
+    cur ^= 1;
+    if (launched >= bound) {
+      if (hipEventSynchronize(ev[cur ^ 1]) != hipSuccess) goto out;
+      bool all = true;
+      for (int64_t i = 0; i < count && all; ++i) all = hstate[(cur ^ 1) * count + i].done != 0;
+      rc = all ? PI_OK : PI_ERR_DEVICE;
+      break;
+    }
+    replays = std::min(replays * 2, 16);
+  }
+out:
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  return rc;
+}
+
+pi_status finish(const Launcher &L, hipStream_t stream, State *dstate, State *hstate, int64_t count) {
+  if (L.go(K_GAUGE_SUM, stream) != hipSuccess || L.go(K_GAUGE_GROUPS, stream) != hipSuccess ||
+      L.go(K_GAUGE_APPLY, stream) != hipSuccess)
+    return PI_ERR_DEVICE;
+  if (hipMemcpyAsync(hstate, dstate, (size_t)count * sizeof(State), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return PI_ERR_DEVICE;
+  return PI_OK;
+}
+
+void fill_info(pi_info *info, const State &s, const pi_plan_s *p, double ms) {
+  if (!info) return;
+  info->outer_iters = s.outer;
+  info->inner_iters_total = s.inner_total;
+  info->eps_R = s.epsR;
+  info->eps_P = s.epsP;
+  info->ms = ms;
+  info->status = s.status;
+  info->components = p->ncomp;
+}
+
+int worst(int a, int b) {
+  // any error outranks PI_OK; keep the first error seen
+  return a != PI_OK ? a : b;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+bool set_user(Inst &in, const pi_plan_s *p, const void *gx, const void *gy, const void *gz, void *P, double tol,
+              int64_t max_iter, uint32_t flags) {
+  if (!gx || !gy || !P) return false;
+  if (p->ndim == 3 && !gz) return false;
+  if (!(tol >= 0.0) || max_iter < 0) return false;
+  in.g[0] = gx;
+  in.g[1] = gy;
+  in.g[2] = p->ndim == 3 ? gz : nullptr;
+  in.Pout = P;
+  in.P0 = (flags & PI_WARM_START) ? P : nullptr;
+  in.tol = tol;
+  in.max_iter = max_iter;
+  in.inner_iters = p->inner_iters;
+  return true;
+}
+
+hipStream_t cap_stream(pi_plan_s *p) {
+  if (!p->cap_stream) (void)hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+  return p->cap_stream;
+}
+
+Launcher single_launcher(pi_plan_s *p) {
+  Launcher L;
+  L.fp64 = p->fp64;
+  L.insts = p->d_inst;
+  L.sts = p->d_state;
+  L.part = p->d_part;
+  L.count = 1;
+  L.grp[p->ndim == 3 ? 1 : 0] = Group{p->d_tab, p->ntab};
+  return L;
+}
+
+}  // namespace
+
+extern "C" pi_status pi_solve(pi_plan_t p, const void *gx, const void *gy, const void *gz, void *P, double tol,
+                              int64_t max_iter, uint32_t flags, pi_info *info, void *stream_) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!p || (flags & ~PI_WARM_START)) return PI_ERR_INVALID_ARG;
+  hipStream_t stream = (hipStream_t)stream_;
+  Inst in = p->inst;
+  if (!set_user(in, p, gx, gy, gz, P, tol, max_iter, flags)) return PI_ERR_INVALID_ARG;
+  State st0 = fresh_state();
+  if (hipMemcpyAsync(p->d_inst, &in, sizeof(Inst), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(p->d_state, &st0, sizeof(State), hipMemcpyHostToDevice, stream) != hipSuccess)
+    return PI_ERR_DEVICE;
+  const Launcher L = single_launcher(p);
+  if (L.go(K_INIT, stream, (flags & PI_WARM_START) ? 1 : 0) != hipSuccess || L.go(K_SOURCE, stream) != hipSuccess)
+    return PI_ERR_DEVICE;
+  const int key = p->inner_iters * 2 + (p->bicgstab ? 1 : 0);
+  if (!p->graph || p->graph_key != key) {
+    if (p->graph) (void)hipGraphExecDestroy(p->graph);
+    p->graph = nullptr;
+    if (capture(L, cap_stream(p), p->inner_iters, p->bicgstab, &p->graph) != hipSuccess) return PI_ERR_DEVICE;
+    p->graph_key = key;
+  }
+  // h_state holds three records: [0] final snapshot, [1..2] polling buffers
+  pi_status rc = iterate(p->graph, stream, p->d_state, p->h_state + 1, 1, max_iter);
+  if (rc != PI_OK) return rc;
+  rc = finish(L, stream, p->d_state, p->h_state, 1);
+  if (rc != PI_OK) return rc;
+  fill_info(info, *p->h_state, p, ms_since(t0));
+  return (pi_status)p->h_state->status;
+}
+
+extern "C" pi_status pi_solve_batched(int64_t count, const pi_plan_t *plans, const void *const *gx,
+                                      const void *const *gy, const void *const *gz, void *const *P,
+                                      const double *tol, int64_t max_iter, uint32_t flags, pi_info *infos,
+                                      void *stream_) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (count < 1 || !plans || !gx || !gy || !P || !tol || (flags & ~PI_WARM_START)) return PI_ERR_INVALID_ARG;
+  hipStream_t stream = (hipStream_t)stream_;
+  const bool fp64 = plans[0] ? plans[0]->fp64 : false;
+  const bool bicg = plans[0] ? plans[0]->bicgstab : false;
+  int inner = 1;
+  std::vector<Inst> host(count);
+  for (int64_t i = 0; i < count; ++i) {
+    pi_plan_s *p = plans[i];
+    if (!p || p->fp64 != fp64 || p->bicgstab != bicg) return PI_ERR_INVALID_ARG;
+    for (int64_t j = 0; j < i; ++j)
+      if (plans[j] == p) return PI_ERR_INVALID_ARG;
+    host[i] = p->inst;
+    if (!set_user(host[i], p, gx[i], gy[i], gz ? gz[i] : nullptr, P[i], tol[i], max_iter, flags))
+      return PI_ERR_INVALID_ARG;
+    inner = std::max(inner, p->inner_iters);
+  }
+  // block tables per dimensionality; partial slots are numbered across both
+  std::vector<Inst *> by[2];
+  std::vector<int64_t> idx[2];
+  for (int64_t i = 0; i < count; ++i) {
+    const int g = host[i].ndim == 3 ? 1 : 0;
+    by[g].push_back(&host[i]);
+    idx[g].push_back(i);
+  }
+  std::vector<BlockEnt> tabs[2];
+  int parts = 0;
+  for (int g = 0; g < 2; ++g) {
+    if (by[g].empty()) continue;
+    int total = 0;
+    tabs[g] = build_table(by[g], parts, &total);
+    // the table names instances by position inside the group; map to batch index
+    for (auto &e : tabs[g])
+      if (e.inst >= 0) e.inst = (int32_t)idx[g][e.inst];
+    parts = total;
+  }
+  Launcher L;
+  L.fp64 = fp64;
+  L.count = (int)count;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  State *hst = nullptr;
+  pi_status rc = PI_ERR_DEVICE;
+  std::vector<State> init(count, fresh_state());
+  if (hipMalloc((void **)&L.insts, count * sizeof(Inst)) != hipSuccess ||
+      hipMalloc((void **)&L.sts, count * sizeof(State)) != hipSuccess ||
+      hipMalloc((void **)&L.part, (size_t)std::max(parts, 1) * 4 * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void **)&hst, 2 * count * sizeof(State), hipHostMallocDefault) != hipSuccess) {
+    rc = PI_ERR_OOM;
+    goto done;
+  }
+  for (int g = 0; g < 2; ++g) {
+    if (tabs[g].empty()) continue;
+    if (hipMalloc((void **)&L.grp[g].tab, tabs[g].size() * sizeof(BlockEnt)) != hipSuccess) {
+      rc = PI_ERR_OOM;
+      goto done;
+    }
+    L.grp[g].ntab = (int)tabs[g].size();
+    if (hipMemcpyAsync(L.grp[g].tab, tabs[g].data(), tabs[g].size() * sizeof(BlockEnt), hipMemcpyHostToDevice,
+                       stream) != hipSuccess)
+      goto done;
+  }
+  if (hipMemcpyAsync(L.insts, host.data(), count * sizeof(Inst), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(L.sts, init.data(), count * sizeof(State), hipMemcpyHostToDevice, stream) != hipSuccess)
+    goto done;
+  if (L.go(K_INIT, stream, (flags & PI_WARM_START) ? 1 : 0) != hipSuccess || L.go(K_SOURCE, stream) != hipSuccess)
+    goto done;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) goto done;
+  if (capture(L, cap, inner, bicg, &exec) != hipSuccess) goto done;
+  rc = iterate(exec, stream, L.sts, hst, count, max_iter);
+  if (rc != PI_OK) goto done;
+  rc = finish(L, stream, L.sts, hst, count);
+  if (rc != PI_OK) goto done;
+  {
+    const double ms = ms_since(t0);
+    int w = PI_OK;
+    for (int64_t i = 0; i < count; ++i) {
+      fill_info(infos ? infos + i : nullptr, hst[i], plans[i], ms);
+      w = worst(w, hst[i].status);
+    }
+    rc = (pi_status)w;
+  }
+done:
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (cap) (void)hipStreamDestroy(cap);
+  (void)hipStreamSynchronize(stream);
+  if (L.insts) (void)hipFree(L.insts);
+  if (L.sts) (void)hipFree(L.sts);
+  if (L.part) (void)hipFree(L.part);
+  for (int g = 0; g < 2; ++g)
+    if (L.grp[g].tab) (void)hipFree(L.grp[g].tab);
+  if (hst) (void)hipHostFree(hst);
+  return rc;
+}
+
+extern "C" pi_status pi_source(pi_plan_t p, const void *gx, const void *gy, const void *gz, void *S, void *stream_) {
+  if (!p || !gx || !gy || !S || (p->ndim == 3 && !gz)) return PI_ERR_INVALID_ARG;
+  hipStream_t stream = (hipStream_t)stream_;
+  Inst in = p->inst;
+  in.g[0] = gx;
+  in.g[1] = gy;
+  in.g[2] = p->ndim == 3 ? gz : nullptr;
+  in.S = S;
+  State st0 = fresh_state();
+  const Launcher L = single_launcher(p);
+  if (hipMemcpyAsync(p->d_inst, &in, sizeof(Inst), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(p->d_state, &st0, sizeof(State), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      L.go(K_SOURCE, stream) != hipSuccess ||
+      hipMemcpyAsync(p->h_state, p->d_state, sizeof(State), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return PI_ERR_DEVICE;
+  return p->h_state->nonfinite ? PI_ERR_NONFINITE : PI_OK;
+}
+
+extern "C" pi_status pi_apply(pi_plan_t p, int op, const void *x, void *y, void *stream_) {
+  if (!p || !x || !y || op < PI_OP_M || op > PI_OP_L || x == y) return PI_ERR_INVALID_ARG;
+  hipStream_t stream = (hipStream_t)stream_;
+  // the operator reads only plan fields of the device instance record, which
+  // every call leaves in place
+  const Launcher L = single_launcher(p);
+  if (L.go(K_APPLY, stream, op, x, y) != hipSuccess) return PI_ERR_DEVICE;
+  return PI_OK;
+}
+
+extern "C" pi_status pi_time_kernel(pi_plan_t p, int kernel, int32_t reps, double *avg_ms, void *stream_) {
+  if (!p || !avg_ms || reps < 1 || kernel < PI_K_OUTER || kernel > PI_K_UPDATE) return PI_ERR_INVALID_ARG;
+  hipStream_t stream = (hipStream_t)stream_;
+  const Launcher L = single_launcher(p);
+  // a mid-solve state: a correction is pending, the search direction is not
+  // the first one, no convergence, never reaching the tolerance
+  Inst in = p->inst;
+  in.tol = -1.0;
+  in.max_iter = INT64_MAX;
+  in.inner_iters = 1 << 30;
+  State st = fresh_state();
+  st.first = 0;
+  st.have_delta = 1;
+  st.inner = 1;
+  st.rr = 1.0;
+  st.alpha = 1e-3;
+  st.beta = 0.5;
+  st.normS2 = 1.0;
+  const KernelId k = kernel == PI_K_OUTER ? K_OUTER : kernel == PI_K_SPMV ? K_CG_SPMV : K_CG_UPDATE;
+  hipEvent_t a = nullptr, b = nullptr;
+  pi_status rc = PI_ERR_DEVICE;
+  float ms = 0.f;
+  if (hipMemcpyAsync(p->d_inst, &in, sizeof(Inst), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(p->d_state, &st, sizeof(State), hipMemcpyHostToDevice, stream) != hipSuccess)
+    return PI_ERR_DEVICE;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) goto out;
+  // the kernel alone: without its finalize the state, and so every launch,
+  // stays the same
+  if (L.go(k, stream, 0, nullptr, nullptr, false) != hipSuccess) goto out;  // warm-up launch
+  if (hipEventRecord(a, stream) != hipSuccess) goto out;
+  for (int i = 0; i < reps; ++i)
+    if (L.go(k, stream, 0, nullptr, nullptr, false) != hipSuccess) goto out;
+  if (hipEventRecord(b, stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+      hipEventElapsedTime(&ms, a, b) != hipSuccess)
+    goto out;
+  *avg_ms = (double)ms / reps;
+  rc = PI_OK;
+out:
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipStreamSynchronize(stream);
+  return rc;
+}
+
+extern "C" const char *pi_status_string(pi_status s) {
+  switch (s) {
+    case PI_OK: return "ok";
+    case PI_ERR_INVALID_ARG: return "invalid argument";
+    case PI_ERR_OOM: return "out of memory";
+    case PI_ERR_NONFINITE: return "non-finite gradient in a data cell";
+    case PI_ERR_NOT_CONVERGED: return "not converged within max_iter outer steps";
+    case PI_ERR_DIVERGED: return "residual became non-finite";
+    case PI_ERR_DEVICE: return "HIP runtime error";
+  }
+  return "unknown status";
+}

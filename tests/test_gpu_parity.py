@@ -1,0 +1,294 @@
+"""Parity of the HIP library (through its C interface) with the CPU oracle.
+
+Sizes span several strips and segments with ragged tails; results are
+compared cell by cell.  Bars: operator applies and the source vector to
+rounding; converged pressure max-abs error <= 1e-11 RMS(P) in FP64 mode and
+<= 1e-5 RMS(P) in FP32 mode against the oracle's fixed point (route O2).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_common import (DEV, announce, fp32_cases, fp64_cases, np_, oracle_for, rel_maxabs, requires_gpu,
+                        small_cases)
+from oracle.solve import fixed_point, gauge, outer_iteration, residual_momentum
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+CASES = small_cases()
+
+
+def _plan(w, fp64, **kw):
+    import paper_2311_16935_amd as pi
+
+    return pi.Plan(w.dims, w.spacing, mask=w.mask, fp64=fp64, **kw)
+
+
+def _grads(w, fp64):
+    dt = torch.float64 if fp64 else torch.float32
+    return [g.to(DEV, dt) for g in w.grads]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_operator_applies(name, make, fp64):
+    import paper_2311_16935_amd as pi
+
+    announce("apply", name, fp64)
+    w = make()
+    sys_ = oracle_for(w)
+    plan = _plan(w, fp64)
+    rng = np.random.default_rng(5)
+    x = np.zeros(sys_.valid.shape)
+    x[sys_.valid] = rng.normal(size=sys_.n)
+    dt = torch.float64 if fp64 else torch.float32
+    xt = torch.tensor(x, dtype=dt, device=DEV)
+    xv = x[sys_.valid]
+    if not fp64:
+        xv = xt.cpu().double().numpy()[sys_.valid]
+    refs = {pi.PI_OP_M: sys_.M @ xv, pi.PI_OP_N: sys_.N @ xv, pi.PI_OP_L: sys_.L @ xv}
+    for op, ref in refs.items():
+        y = np_(plan.apply(op, xt)).astype(np.float64)
+        assert np.all(y[~sys_.valid] == 0)
+        err = np.abs(y[sys_.valid] - ref).max() / np.abs(ref).max()
+        assert err < (1e-14 if fp64 else 2e-6), (op, err)
+    plan.close()
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_source(name, make, fp64):
+    announce("source", name, fp64)
+    w = make()
+    sys_ = oracle_for(w)
+    plan = _plan(w, fp64)
+    g = _grads(w, fp64)
+    S = np_(plan.source(g)).astype(np.float64)
+    ref = sys_.source([np_(x).astype(np.float64) for x in g])
+    assert np.all(S[~sys_.valid] == 0)
+    err = np.abs(S[sys_.valid] - ref).max() / np.abs(ref).max()
+    assert err < (1e-14 if fp64 else 1e-7), err
+    plan.close()
+
+
+def _converged_fp64(res):
+    # stop at 1e-14, or where rounding of the FP64 residual stalls just above it
+    return res.status == 0 or (res.status == 4 and res.info["eps_R"] <= 1e-13)
+
+
+F64 = fp64_cases()
+F32 = fp32_cases()
+
+
+@pytest.mark.parametrize("name,make", F64, ids=[c[0] for c in F64])
+def test_solve_fp64_matches_fixed_point(name, make):
+    announce("solve-fp64", name)
+    w = make()
+    sys_ = oracle_for(w)
+    plan = _plan(w, True)
+    g = _grads(w, True)
+    res = plan.solve(g, tol=1e-14, max_iter=300000, check=False)
+    assert _converged_fp64(res), res.info
+    P = np_(res.P)
+    assert np.all(np.isnan(P[~sys_.valid]))
+    ref = fixed_point(sys_, sys_.source([np_(x) for x in g]))
+    err = rel_maxabs(P[sys_.valid], ref)
+    assert err <= 1e-11, err
+    plan.close()
+
+
+@pytest.mark.parametrize("name,make", F32, ids=[c[0] for c in F32])
+def test_solve_fp32_matches_fixed_point(name, make):
+    announce("solve-fp32", name)
+    w = make()
+    sys_ = oracle_for(w)
+    plan = _plan(w, False)
+    g = _grads(w, False)
+    res = plan.solve(g, tol=1e-10, max_iter=300000)
+    assert res.status == 0, res.info
+    P = np_(res.P).astype(np.float64)
+    assert np.all(np.isnan(P[~sys_.valid]))
+    ref = fixed_point(sys_, sys_.source([np_(x).astype(np.float64) for x in g]))
+    err = rel_maxabs(P[sys_.valid], ref)
+    assert err <= 1e-5, err
+    plan.close()
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_reported_residual_and_gauge(fp64):
+    announce("residual", fp64)
+    w = synth.random_small(44, 2, (90, 61), mask_frac=0.12)
+    sys_ = oracle_for(w)
+    plan = _plan(w, fp64)
+    g = _grads(w, fp64)
+    res = plan.solve(g, tol=1e-7)
+    assert res.status == 0 and res.info["eps_R"] <= 1e-7
+    P = np_(res.P).astype(np.float64)[sys_.valid]
+    S = sys_.source([np_(x).astype(np.float64) for x in g])
+    eR = residual_momentum(sys_, S, P)
+    if fp64:
+        assert eR == pytest.approx(res.info["eps_R"], rel=1e-6)
+    else:
+        # the returned float field carries its own rounding: its residual is
+        # bounded by the FP64 iterate's plus that of rounding the exact
+        # fixed point to float
+        ref = fixed_point(sys_, S)
+        floor = residual_momentum(sys_, S, ref.astype(np.float32).astype(np.float64))
+        assert eR <= res.info["eps_R"] + 2.0 * floor, (eR, floor)
+    from oracle.solve import components
+    k, lab = components(sys_)
+    assert res.info["components"] == k
+    rms = np.sqrt(np.mean(P**2))
+    for c in range(k):
+        assert abs(P[lab == c].mean()) < (1e-13 if fp64 else 1e-6) * rms
+    plan.close()
+
+
+def test_bicgstab_inner_solver():
+    announce("bicgstab")
+    w = synth.random_small(42, 3, (24, 17, 13), mask_frac=0.1)
+    sys_ = oracle_for(w)
+    plan = _plan(w, True, bicgstab=True, inner_iters=2)
+    g = _grads(w, True)
+    res = plan.solve(g, tol=1e-14, max_iter=200000, check=False)
+    assert _converged_fp64(res), res.info
+    ref = fixed_point(sys_, sys_.source([np_(x) for x in g]))
+    assert rel_maxabs(np_(res.P)[sys_.valid], ref) <= 1e-11
+    plan.close()
+
+
+def test_exact_inner_solve_follows_algorithm_1():
+    # With many inner iterations each outer step is Eq. MatrixEquation solved
+    # exactly, so the GPU trajectory follows the oracle's route O1.
+    announce("trajectory")
+    w = synth.random_small(22, 2, (23, 19), mask_frac=0.1)
+    sys_ = oracle_for(w)
+    g = _grads(w, True)
+    S = sys_.source([np_(x) for x in g])
+    ref = outer_iteration(sys_, S, tol=0.0, max_iter=5)
+    plan = _plan(w, True, bicgstab=True, inner_iters=200)
+    res = plan.solve(g, tol=0.0, max_iter=5)
+    assert res.status == 4 and res.info["outer_iters"] == 5
+    assert rel_maxabs(np_(res.P)[sys_.valid], gauge(sys_, ref.P)) < 1e-9
+    plan.close()
+
+
+def test_masked_cells_are_ignored():
+    announce("masked-nan")
+    w = synth.random_small(23, 2, (77, 51), mask_frac=0.15)
+    sys_ = oracle_for(w)
+    g = _grads(w, True)
+    assert any(torch.isnan(x).any() for x in g)   # NaN sits in masked cells
+    plan = _plan(w, True)
+    a = np_(plan.solve(g, tol=1e-8, max_iter=100000).P)
+    g2 = [torch.where(torch.isnan(x), torch.full_like(x, 1e30), x) for x in g]
+    b = np_(plan.solve(g2, tol=1e-8, max_iter=100000).P)
+    assert np.array_equal(a[sys_.valid], b[sys_.valid])
+    plan.close()
+
+
+def test_error_paths():
+    import paper_2311_16935_amd as pi
+
+    announce("errors")
+    w = synth.random_small(24, 2, (40, 30), mask_frac=0.1)
+    sys_ = oracle_for(w)
+    plan = _plan(w, True)
+    g = _grads(w, True)
+    # a NaN inside a data cell
+    bad = [x.clone() for x in g]
+    yy, xx = np.argwhere(sys_.valid)[7]
+    bad[1][yy, xx] = float("nan")
+    r = plan.solve(bad, tol=1e-8, check=False)
+    assert r.status == pi.PI_ERR_NONFINITE
+    with pytest.raises(pi.PiError):
+        plan.source(bad)
+    # max_iter reached: last iterate returned, gauged
+    r = plan.solve(g, tol=1e-14, max_iter=3, check=False)
+    assert r.status == pi.PI_ERR_NOT_CONVERGED and r.info["outer_iters"] == 3
+    assert np.isfinite(np_(r.P)[sys_.valid]).all()
+    # invalid arguments
+    with pytest.raises(pi.PiError):
+        pi.pi_plan(2, (0, 5), (1.0, 1.0))
+    with pytest.raises(pi.PiError):
+        pi.pi_plan(2, (5, 5), (1.0, -1.0))
+    with pytest.raises(pi.PiError):
+        pi.pi_plan(2, (5, 5), (1.0, 1.0), mask=torch.zeros(5, 5, dtype=torch.uint8))
+    rc, _ = pi.pi_solve(plan.handle, g[0], g[1], None, torch.empty_like(g[0]), -1.0, 10)
+    assert rc == pi.PI_ERR_INVALID_ARG
+    plan.close()
+
+
+def test_warm_start_and_offsets():
+    announce("warm-start")
+    w = synth.random_small(25, 2, (60, 45), mask_frac=0.1)
+    sys_ = oracle_for(w)
+    plan = _plan(w, True)
+    g = _grads(w, True)
+    base = plan.solve(g, tol=1e-12)
+    P0 = base.P.clone()
+    P0[torch.isnan(P0)] = 0.0
+    P0 += 5.0
+    r = plan.solve(g, P=P0, tol=1e-12, warm_start=True)
+    assert r.info["outer_iters"] == 0
+    assert np.nanmax(np.abs(np_(r.P) - np_(base.P))) < 1e-12 * np.sqrt(np.nanmean(np_(base.P) ** 2))
+    # a constant added to the true pressure gives an identical input and result
+    zero = [torch.zeros_like(x) for x in g]
+    z = plan.solve(zero, tol=1e-9)
+    assert z.status == 0 and z.info["outer_iters"] == 0
+    assert np.all(np_(z.P)[sys_.valid] == 0)
+    plan.close()
+
+
+def test_batched_matches_single_solves():
+    import paper_2311_16935_amd as pi
+
+    announce("batched")
+    ws = [synth.random_small(31, 2, (150, 70), mask_frac=0.1),
+          synth.random_small(32, 3, (40, 22, 31), mask_frac=0.05),
+          synth.random_small(33, 2, (64, 200), mask_frac=0.0),
+          synth.random_small(34, 3, (17, 9, 12), anisotropic=False, mask_frac=0.0)]
+    for fp64 in (False, True):
+        plans = [_plan(w, fp64) for w in ws]
+        grads = [_grads(w, fp64) for w in ws]
+        tols = [1e-6, 1e-7, 1e-6, 1e-8]
+        singles = [p.solve(g, tol=t, max_iter=100000) for p, g, t in zip(plans, grads, tols)]
+        rc, Ps, infos = pi.solve_batched(plans, grads, tol=tols, max_iter=100000)
+        assert rc == 0
+        for s, P, info in zip(singles, Ps, infos):
+            assert info["outer_iters"] == s.info["outer_iters"]
+            assert torch.equal(torch.nan_to_num(P, nan=7.0), torch.nan_to_num(s.P, nan=7.0))
+        # an instance with zero source and a slow one in the same batch
+        zero = [torch.zeros_like(x) for x in grads[0]]
+        rc, Ps, infos = pi.solve_batched(plans[:2], [zero, grads[1]], tol=[1e-6, 1e-8], max_iter=100000)
+        assert rc == 0 and infos[0]["outer_iters"] == 0 and infos[1]["outer_iters"] > 50
+        for p in plans:
+            p.close()
+
+
+def test_sin64_config():
+    # 64^2, unit spacing, P = sin(2 pi x) cos(2 pi y) with 5 % gradient noise,
+    # FP64, solved to eps_R <= 1e-10; against the oracle's Algorithm 1 (exact
+    # inner solves) run to the same threshold and its fixed point.
+    announce("sin64")
+    w = synth.config_sin64()
+    sys_ = oracle_for(w)
+    g = _grads(w, True)
+    S = sys_.source([np_(x) for x in g])
+    plan = _plan(w, True)
+    r = plan.solve(g, tol=1e-10)
+    assert r.status == 0 and r.info["eps_R"] <= 1e-10
+    P = np_(r.P)[sys_.valid]
+    assert residual_momentum(sys_, S, P) <= 1.01e-10
+    o1 = outer_iteration(sys_, S, tol=1e-10, max_iter=100000)
+    ref = fixed_point(sys_, S)
+    # both sit within their residual-limited distance of the fixed point
+    e_gpu = rel_maxabs(P, ref)
+    e_o1 = rel_maxabs(gauge(sys_, o1.P), ref)
+    assert e_gpu < 1e-7 and e_o1 < 1e-7
+    r2 = plan.solve(g, tol=1e-14, max_iter=200000, check=False)
+    assert _converged_fp64(r2), r2.info
+    assert rel_maxabs(np_(r2.P)[sys_.valid], ref) <= 1e-11
+    plan.close()

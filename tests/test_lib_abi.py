@@ -1,0 +1,61 @@
+"""The C interface: the built library loads and exports every function that
+the headers declare (no GPU needed, no compute call made)."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = ["include/pi.h"]
+LIBS = {"include/pi.h": "paper_2311_16935_amd/libpi.so"}
+
+
+def declared(header):
+    txt = open(os.path.join(ROOT, header)).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(pi\w*)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.mark.parametrize("header", HEADERS)
+def test_library_exports_every_declared_function(header):
+    lib_path = os.path.join(ROOT, LIBS[header])
+    assert os.path.exists(lib_path), "build the library first (__graft_entry__.build())"
+    names = declared(header)
+    assert len(names) >= 8
+    lib = ctypes.CDLL(lib_path)
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", lib_path], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (pi\w+)", out))
+    assert set(names) <= exported
+
+
+def test_binding_names_match_header():
+    import paper_2311_16935_amd as pi
+
+    names = declared("include/pi.h")
+    assert sorted(pi.EXPORTED) == names
+    for n in names:
+        assert callable(getattr(pi, n))
+
+
+def test_status_strings_without_gpu():
+    import paper_2311_16935_amd as pi
+
+    assert pi.pi_status_string(0) == "ok"
+    assert "max_iter" in pi.pi_status_string(4)
+    assert pi.pi_status_string(99) == "unknown status"
+
+
+def test_plan_argument_checks_fail_before_touching_the_device():
+    import paper_2311_16935_amd as pi
+
+    for args in [(4, (5, 5), (1.0, 1.0)), (2, (0, 5), (1.0, 1.0)), (2, (5, 5), (1.0, 0.0)),
+                 (2, (5, 5), (1.0, float("nan"))), (3, (1 << 11, 1 << 11, 1 << 10), (1.0, 1.0, 1.0))]:
+        with pytest.raises(pi.PiError) as e:
+            pi.pi_plan(*args)
+        assert e.value.status == pi.PI_ERR_INVALID_ARG
