@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 # algorithmic bytes per cell per launch (FP32 mode): what each kernel must read
 # and write once, neighbour re-reads excluded
 BYTES_PER_CELL = {
-    "k_outer": 8 + 4 + 4 + 4 + 8 + 4,   # P, delta, S, code in; P', r out
+    "k_outer": 8 + 4 + 8 + 4 + 8 + 4,   # P, delta, S (FP64), code in; P', r out
     "k_cg_spmv": 4 + 4 + 4 + 4 + 4,     # r, p, code in; p', q out
     "k_cg_update": 4 * 4 + 2 * 4,       # p, q, r, delta in; delta, r out
 }
@@ -50,7 +50,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--mode", choices=("solve", "kernels"), default="solve",
+                    help="kernels: only time the outer-step kernels and a copy of known size (for counters)")
     return ap.parse_args()
+
+
+def progress(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def traffic_from_profile(kernel, n, src_hash):
@@ -112,6 +118,32 @@ def cpu_baseline(n_sample, seed, n_target, tol):
     }
 
 
+def kernel_mode(args, pi, plan, grads, P, ncell):
+    """Few dispatches: fill the workspace with four outer steps, then launch
+    each outer-step kernel a few times, then run an element-wise int32 kernel
+    over ncell elements (reads and writes 4 * ncell bytes) as the counter
+    yardstick."""
+    import torch
+
+    plan.solve(grads, P=P, tol=0.0, max_iter=4, check=False)
+    res = {}
+    for name, kid in (("k_outer", pi.PI_K_OUTER), ("k_cg_spmv", pi.PI_K_SPMV), ("k_cg_update", pi.PI_K_UPDATE)):
+        ms = pi.pi_time_kernel(plan.handle, kid, args.kernel_reps)
+        res[name] = {"avg_ms": ms, "launches": args.kernel_reps + 1,
+                     "alg_bytes": BYTES_PER_CELL[name] * ncell,
+                     "achieved_GBs": BYTES_PER_CELL[name] * ncell / (ms * 1e-3) / 1e9}
+    # yardstick with a kernel name nothing else here uses: reads and writes
+    # 4 bytes per element
+    x = torch.randint(0, 1 << 30, (ncell,), dtype=torch.int32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(args.kernel_reps):
+        torch.bitwise_not(x, out=y)
+    torch.cuda.synchronize()
+    res["bitwise_not"] = {"bytes_read": 4 * ncell, "bytes_written": 4 * ncell, "launches": args.kernel_reps}
+    print(json.dumps({"mode": "kernels", "n": args.n, "cells": ncell, "kernels": res,
+                      "kernel_source_sha256": kernel_source_hash()}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -131,14 +163,20 @@ def main():
     plan = pi.Plan((n, n, n), w.spacing, fp64=False, inner_iters=args.inner)
     P = torch.empty((n, n, n), dtype=torch.float32, device=dev)
     ncell = n ** 3
-    for _ in range(args.warmup):
-        plan.solve(grads, P=P, tol=args.tol)
+    progress(f"plan ready: {n}^3, tile {pi.pi_get_tile(plan.handle)}, {plan.workspace_bytes / 2**30:.2f} GiB")
+    if args.mode == "kernels":
+        kernel_mode(args, pi, plan, grads, P, ncell)
+        return
+    for i in range(args.warmup):
+        r = plan.solve(grads, P=P, tol=args.tol)
+        progress(f"warmup {i}: {r.info['ms'] / 1e3:.2f} s, {r.info['outer_iters']} outer steps")
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         r = plan.solve(grads, P=P, tol=args.tol)
         infos.append(r.info)
+        progress(f"step {i}: {r.info['ms'] / 1e3:.2f} s")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     sec = elapsed / max(1, args.steps)

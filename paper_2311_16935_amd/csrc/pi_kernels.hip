@@ -22,19 +22,49 @@
 
 namespace pi {
 
+// Buffers reached through the instance record are generic pointers to the
+// compiler, which would then emit flat accesses that wait on both the vector
+// memory and LDS counters; every hot buffer is therefore cast to the global
+// address space once.
+#define PI_G __attribute__((address_space(1)))
+template <typename T>
+__device__ inline PI_G T *gp(void *p) {
+  return (PI_G T *)p;
+}
+template <typename T>
+__device__ inline const PI_G T *gp(const void *p) {
+  return (const PI_G T *)p;
+}
+
 // ---------------------------------------------------------------------------
 // work decomposition
 // ---------------------------------------------------------------------------
+// Everything a wave needs while it walks its segment, copied out of the
+// instance record once: the compiler cannot keep fields of a global struct
+// in registers across the kernel's own stores.
 struct Walk {
   int64_t base;   // storage index of this lane's column at march position 0
+  int64_t sm;     // stride of the march axis
+  const PI_G uint32_t *code;
   int m0, m1;     // march range of this wave (uniform over the wave)
+  int nm;         // length of the march axis
+  int nx, ny;
   int x;          // x of this lane
   int row;        // y of this wave's strip (3-D)
   bool act;       // lane owns a cell column inside the grid
 };
 
 __device__ inline Walk make_walk(const Inst &in, int lb) {
-  Walk k{0, 0, 0, 0, 0, false};
+  Walk k;
+  k.sm = in.sm;
+  k.code = gp<uint32_t>(in.code);
+  k.nm = in.nm;
+  k.nx = in.nx;
+  k.ny = in.ny;
+  k.m0 = k.m1 = 0;
+  k.x = k.row = 0;
+  k.base = 0;
+  k.act = false;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t)lb * kWavesPerBlock + wave;
@@ -59,7 +89,9 @@ __device__ inline Walk make_walk(const Inst &in, int lb) {
   k.m1 = min(k.m0 + in.mseg, in.nm);
   k.act = k.x < in.nx;
   k.row = (int)row;
-  k.base = (int64_t)k.x + row * in.srow;
+  // lanes past the end of a partial strip address the strip's last cell, so
+  // that every load is in bounds without a branch; they never store
+  k.base = (int64_t)min(k.x, in.nx - 1) + row * in.srow;
   return k;
 }
 
@@ -87,34 +119,42 @@ struct Plane {
 //   store(c, out)
 template <int ND, typename V, typename A, typename Out, typename Load, typename Aux, typename Body,
           typename Store>
-__device__ inline void march(const Inst &in, const Walk &wk, Load load, Aux aux, Body body, Store store) {
+__device__ inline void march(const Walk &wk, Load load, Aux aux, Body body, Store store) {
   if (wk.m1 <= wk.m0) return;  // uniform over the wave
   const int lane = threadIdx.x & 63;
-  const bool hasN = ND == 3 && wk.row + 1 < in.ny, hasS = ND == 3 && wk.row > 0;
-  const bool edgeW = lane == 0 && wk.x > 0, edgeE = lane == kWave - 1 && wk.x + 1 < in.nx;
-  const int64_t snx = in.nx;
+  const bool hasN = ND == 3 && wk.row + 1 < wk.ny, hasS = ND == 3 && wk.row > 0;
+  const bool edgeW = lane == 0 && wk.x > 0, edgeE = lane == kWave - 1 && wk.x + 1 < wk.nx;
+  const int64_t snx = wk.nx;
+  // neighbour offsets resolved once; a neighbour that does not exist reads
+  // the cell itself and is zeroed, so no load sits behind a branch
+  const int64_t offN = hasN ? snx : 0, offS = hasS ? -snx : 0;
+  const int64_t offE = edgeW ? -1 : edgeE ? 1 : 0;
+  const bool hasEdge = edgeW || edgeE;
+  const PI_G uint32_t *code = wk.code;
   auto fetch = [&](int64_t c, Plane<V, A> &pl) {
     pl.v = load(c);
-    pl.code = in.code[c];
+    pl.code = code[c];
     pl.aux = aux(c);
     if (ND == 3) {
-      pl.vN = hasN ? load(c + snx) : V(0);
-      pl.vS = hasS ? load(c - snx) : V(0);
+      const V n = load(c + offN), s = load(c + offS);
+      pl.vN = hasN ? n : V(0);
+      pl.vS = hasS ? s : V(0);
     }
-    pl.vEdge = edgeW ? load(c - 1) : edgeE ? load(c + 1) : V(0);
+    const V e = load(c + offE);
+    pl.vEdge = hasEdge ? e : V(0);
   };
-  int64_t c = wk.base + (int64_t)wk.m0 * in.sm;
-  V prev = (wk.act && wk.m0 > 0) ? load(c - in.sm) : V(0);
-  Plane<V, A> cur{}, nxt{};
-  if (wk.act) fetch(c, cur);
-  for (int m = wk.m0; m < wk.m1; ++m, c += in.sm) {
-    nxt.v = V(0);
-    if (wk.act && m + 1 < in.nm) {
-      if (m + 1 < wk.m1)
-        fetch(c + in.sm, nxt);
-      else
-        nxt.v = load(c + in.sm);  // last plane of the segment: its successor is only a neighbour
-    }
+  const int64_t sm = wk.sm;
+  int64_t c = wk.base + (int64_t)wk.m0 * sm;
+  V prev = wk.m0 > 0 ? load(c - sm) : V(0);
+  Plane<V, A> cur, nxt;
+  fetch(c, cur);
+  for (int m = wk.m0; m < wk.m1; ++m, c += sm) {
+    // uniform over the wave: the whole next plane, or only its values when
+    // it is the next segment's first plane, or nothing past the grid
+    if (m + 1 < wk.m1)
+      fetch(c + sm, nxt);
+    else
+      nxt.v = m + 1 < wk.nm ? load(c + sm) : V(0);
     V vW = __shfl_up(cur.v, 1, kWave);
     V vE = __shfl_down(cur.v, 1, kWave);
     if (lane == 0) vW = cur.vEdge;
@@ -128,16 +168,17 @@ __device__ inline void march(const Inst &in, const Walk &wk, Load load, Aux aux,
 // Stream over the cells of one wave's segment, kStream cells per lane at a
 // time: f.load(c, u) for all u first, then f.apply(c, u).
 template <typename F>
-__device__ inline void stream(const Inst &in, const Walk &wk, F &f) {
+__device__ inline void stream(const Walk &wk, F &f) {
   if (!wk.act) return;
+  const int64_t sm = wk.sm;
   for (int m = wk.m0; m < wk.m1; m += kStream) {
-    const int64_t cm = wk.base + (int64_t)m * in.sm;
+    const int64_t cm = wk.base + (int64_t)m * sm;
 #pragma unroll
     for (int u = 0; u < kStream; ++u)
-      if (m + u < wk.m1) f.load(cm + (int64_t)u * in.sm, u);
+      if (m + u < wk.m1) f.load(cm + (int64_t)u * sm, u);
 #pragma unroll
     for (int u = 0; u < kStream; ++u)
-      if (m + u < wk.m1) f.apply(cm + (int64_t)u * in.sm, u);
+      if (m + u < wk.m1) f.apply(cm + (int64_t)u * sm, u);
   }
 }
 
@@ -204,12 +245,20 @@ __global__ __launch_bounds__(kBlock) void k_init(const BlockEnt *tab, const Inst
   const Walk wk = make_walk(in, e.lb);
   const T *P0 = (const T *)in.P0;
   double *P = in.P[0];
+  T *d = (T *)in.d;
+  T *p0 = (T *)in.p[0], *p1 = (T *)in.p[1], *v = (T *)in.bs[1];
   int bad = 0;
   if (wk.act) {
-    int64_t c = wk.base + (int64_t)wk.m0 * in.sm;
-    for (int m = wk.m0; m < wk.m1; ++m, c += in.sm) {
+    int64_t c = wk.base + (int64_t)wk.m0 * wk.sm;
+    for (int m = wk.m0; m < wk.m1; ++m, c += wk.sm) {
+      // no correction before the first outer step, and finite search
+      // directions for the first inner iteration (which scales them by 0)
+      d[c] = T(0);
+      p0[c] = T(0);
+      p1[c] = T(0);
+      if (v) v[c] = T(0);
       double v = 0.0;
-      if (warm && (in.code[c] & kValidBit)) {
+      if (warm && (wk.code[c] & kValidBit)) {
         v = (double)P0[c];
         if (!isfinite(v)) {
           bad = 1;
@@ -239,12 +288,15 @@ __global__ __launch_bounds__(kBlock) void k_source(const BlockEnt *tab, const In
   const int bits = dir_bits(ND);
   const int64_t off[6] = {1, -1, (int64_t)in.nx, -(int64_t)in.nx, ND == 3 ? (int64_t)in.nx * in.ny : 0,
                           ND == 3 ? -(int64_t)in.nx * in.ny : 0};
+  double w[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) w[d] = -0.5 * in.dsig[d] * in.a[d];
   double acc[1] = {0.0};
   int bad = 0;
   if (wk.act) {
-    int64_t c = wk.base + (int64_t)wk.m0 * in.sm;
-    for (int m = wk.m0; m < wk.m1; ++m, c += in.sm) {
-      const uint32_t cd = in.code[c];
+    int64_t c = wk.base + (int64_t)wk.m0 * wk.sm;
+    for (int m = wk.m0; m < wk.m1; ++m, c += wk.sm) {
+      const uint32_t cd = wk.code[c];
       double s = 0.0;
       if (cd & kValidBit) {
         double own[3];
@@ -258,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_source(const BlockEnt *tab, const In
           if (dstate(cd, d, bits)) {
             const int a = d >> 1;
             const double nb = (double)g[a][c + off[d]];
-            s -= in.dsig[d] * in.a[d] * 0.5 * (nb + own[a]);
+            s += w[d] * (nb + own[a]);
           }
         }
       }
@@ -285,37 +337,41 @@ __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Ins
   const Walk wk = make_walk(in, e.lb);
   const int cur = st->Pcur;
   const bool hd = st->have_delta != 0;
-  const double *Pold = in.P[cur];
-  double *Pnew = in.P[cur ^ 1];
-  const T *dl = (const T *)in.d;
-  const double *S = in.S64;
-  T *res = (T *)in.res;
+  const PI_G double *Pold = gp<double>(in.P[cur]);
+  PI_G double *Pnew = gp<double>(in.P[cur ^ 1]);
+  const PI_G T *dl = gp<T>(in.d);
+  const PI_G double *S = gp<double>(in.S64);
+  PI_G T *res = gp<T>(in.res);
   const int bits = dir_bits(ND);
+  double a[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) a[d] = in.a[d];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   struct Out {
     double p, r;
   };
-  auto load = [&](int64_t c) -> double { return hd ? Pold[c] + (double)dl[c] : Pold[c]; };
+  // delta is zero before the first outer step (set when the solve starts)
+  auto load = [&](int64_t c) -> double { return Pold[c] + (double)dl[c]; };
   struct Aux {
     double S, d;
   };
-  auto aux = [&](int64_t c) -> Aux { return Aux{S[c], hd ? (double)dl[c] : 0.0}; };
+  auto aux = [&](int64_t c) -> Aux { return Aux{S[c], (double)dl[c]}; };
   auto body = [&](int64_t c, const Plane<double, Aux> &pl, double vW, double vE, double vP,
                   double vN) -> Out {
     const uint32_t cd = pl.code;
     if (!(cd & kValidBit)) return Out{0.0, 0.0};
     const double vC = pl.v;
     double Lp = 0.0;
-    if (dstate(cd, DE, bits)) Lp += in.a[DE] * (vC - vE);
-    if (dstate(cd, DW, bits)) Lp += in.a[DW] * (vC - vW);
+    if (dstate(cd, DE, bits)) Lp += a[DE] * (vC - vE);
+    if (dstate(cd, DW, bits)) Lp += a[DW] * (vC - vW);
     if (ND == 3) {
-      if (dstate(cd, DN, bits)) Lp += in.a[DN] * (vC - pl.vN);
-      if (dstate(cd, DS, bits)) Lp += in.a[DS] * (vC - pl.vS);
-      if (dstate(cd, DF, bits)) Lp += in.a[DF] * (vC - vN);
-      if (dstate(cd, DB, bits)) Lp += in.a[DB] * (vC - vP);
+      if (dstate(cd, DN, bits)) Lp += a[DN] * (vC - pl.vN);
+      if (dstate(cd, DS, bits)) Lp += a[DS] * (vC - pl.vS);
+      if (dstate(cd, DF, bits)) Lp += a[DF] * (vC - vN);
+      if (dstate(cd, DB, bits)) Lp += a[DB] * (vC - vP);
     } else {
-      if (dstate(cd, DN, bits)) Lp += in.a[DN] * (vC - vN);
-      if (dstate(cd, DS, bits)) Lp += in.a[DS] * (vC - vP);
+      if (dstate(cd, DN, bits)) Lp += a[DN] * (vC - vN);
+      if (dstate(cd, DS, bits)) Lp += a[DS] * (vC - vP);
     }
     const double r = pl.aux.S - Lp;
     const double rt = (double)(T)r;
@@ -329,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Ins
     Pnew[c] = o.p;
     res[c] = (T)o.r;
   };
-  march<ND, double, Aux, Out>(in, wk, load, aux, body, store);
+  march<ND, double, Aux, Out>(wk, load, aux, body, store);
   publish<4>(in, part, e.lb, acc);
 }
 
@@ -345,19 +401,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const BlockEnt *tab, const I
   __shared__ T lut[6][kStates];
   load_lut<T>(in.lut_np1, lut);
   const Walk wk = make_walk(in, e.lb);
-  const bool first = st->first != 0;
+  // beta is 0 on the first iteration and the old direction is finite, so
+  // the direction update needs no branch
   const T beta = (T)st->beta;
   const int pc = st->pcur;
-  const T *pold = (const T *)in.p[pc];
-  T *pnew = (T *)in.p[pc ^ 1];
-  const T *res = (const T *)in.res;
-  T *q = (T *)in.q;
+  const PI_G T *pold = gp<T>(in.p[pc]);
+  PI_G T *pnew = gp<T>(in.p[pc ^ 1]);
+  const PI_G T *res = gp<T>(in.res);
+  PI_G T *q = gp<T>(in.q);
   const int bits = dir_bits(ND);
   double acc[1] = {0.0};
   struct Out {
     T p, q;
   };
-  auto load = [&](int64_t c) -> T { return first ? res[c] : res[c] + beta * pold[c]; };
+  auto load = [&](int64_t c) -> T { return res[c] + beta * pold[c]; };
   auto body = [&](int64_t c, const Plane<T, int> &pl, T vW, T vE, T vP, T vN) -> Out {
     const uint32_t cd = pl.code;
     const T vC = pl.v;
@@ -382,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const BlockEnt *tab, const I
     pnew[c] = o.p;
     q[c] = o.q;
   };
-  march<ND, T, int, Out>(in, wk, load, [](int64_t) { return 0; }, body, store);
+  march<ND, T, int, Out>(wk, load, [](int64_t) { return 0; }, body, store);
   publish<1>(in, part, e.lb, acc);
 }
 
@@ -390,8 +447,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const BlockEnt *tab, const I
 // r <- r - alpha q, r.r
 template <typename T>
 struct CgUpdate {
-  const T *p, *q;
-  T *res, *d;
+  const PI_G T *p, *q;
+  PI_G T *res, *d;
   T alpha;
   bool first;
   double acc;
@@ -417,14 +474,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const BlockEnt *tab, const
   if (skip_inner(in, st)) return;
   const Walk wk = make_walk(in, e.lb);
   CgUpdate<T> f;
-  f.p = (const T *)in.p[st->pcur];
-  f.q = (const T *)in.q;
-  f.res = (T *)in.res;
-  f.d = (T *)in.d;
+  f.p = gp<T>(in.p[st->pcur]);
+  f.q = gp<T>(in.q);
+  f.res = gp<T>(in.res);
+  f.d = gp<T>(in.d);
   f.alpha = (T)st->alpha;
   f.first = st->inner == 0;
   f.acc = 0.0;
-  stream(in, wk, f);
+  stream(wk, f);
   double acc[1] = {f.acc};
   publish<1>(in, part, e.lb, acc);
 }
@@ -441,21 +498,20 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_p(const BlockEnt *tab, con
   __shared__ T lut[6][kStates];
   load_lut<T>(in.lut_np1, lut);
   const Walk wk = make_walk(in, e.lb);
-  const bool first = st->first != 0;
   const T beta = (T)st->beta, omega = (T)st->omega;
   const int pc = st->pcur;
-  const T *pold = (const T *)in.p[pc];
-  T *pnew = (T *)in.p[pc ^ 1];
-  const T *res = (const T *)in.res;
-  const T *v = (const T *)in.bs[1];
-  const T *rhat = (const T *)in.bs[0];
-  T *vnew = (T *)in.q;
+  const PI_G T *pold = gp<T>(in.p[pc]);
+  PI_G T *pnew = gp<T>(in.p[pc ^ 1]);
+  const PI_G T *res = gp<T>(in.res);
+  const PI_G T *v = gp<T>(in.bs[1]);
+  const PI_G T *rhat = gp<T>(in.bs[0]);
+  PI_G T *vnew = gp<T>(in.q);
   const int bits = dir_bits(ND);
   double acc[1] = {0.0};
   struct Out {
     T p, v;
   };
-  auto load = [&](int64_t c) -> T { return first ? res[c] : res[c] + beta * (pold[c] - omega * v[c]); };
+  auto load = [&](int64_t c) -> T { return res[c] + beta * (pold[c] - omega * v[c]); };
   auto body = [&](int64_t c, const Plane<T, int> &pl, T vW, T vE, T vP, T vN) -> Out {
     const uint32_t cd = pl.code;
     const T vC = pl.v;
@@ -480,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_p(const BlockEnt *tab, con
     pnew[c] = o.p;
     vnew[c] = o.v;
   };
-  march<ND, T, int, Out>(in, wk, load, [](int64_t) { return 0; }, body, store);
+  march<ND, T, int, Out>(wk, load, [](int64_t) { return 0; }, body, store);
   publish<1>(in, part, e.lb, acc);
 }
 
@@ -494,11 +550,11 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_s(const BlockEnt *tab, con
   load_lut<T>(in.lut_np1, lut);
   const Walk wk = make_walk(in, e.lb);
   const T alpha = (T)st->alpha;
-  const T *res = (const T *)in.res;
-  const T *vnew = (const T *)in.q;
-  T *v = (T *)in.bs[1];
-  T *s_out = (T *)in.bs[2];
-  T *t_out = (T *)in.bs[3];
+  const PI_G T *res = gp<T>(in.res);
+  const PI_G T *vnew = gp<T>(in.q);
+  PI_G T *v = gp<T>(in.bs[1]);
+  PI_G T *s_out = gp<T>(in.bs[2]);
+  PI_G T *t_out = gp<T>(in.bs[3]);
   const int bits = dir_bits(ND);
   double acc[2] = {0.0, 0.0};
   struct Out {
@@ -532,15 +588,15 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_s(const BlockEnt *tab, con
     s_out[c] = o.s;
     t_out[c] = o.t;
   };
-  march<ND, T, int, Out>(in, wk, load, [](int64_t) { return 0; }, body, store);
+  march<ND, T, int, Out>(wk, load, [](int64_t) { return 0; }, body, store);
   publish<2>(in, part, e.lb, acc);
 }
 
 // phase 3: delta <- delta + alpha p + omega s, r <- s - omega t, rhat.r
 template <typename T>
 struct BicgUpdate {
-  const T *p, *s, *t, *rhat;
-  T *res, *d;
+  const PI_G T *p, *s, *t, *rhat;
+  PI_G T *res, *d;
   T alpha, omega;
   bool first;
   double acc;
@@ -567,17 +623,17 @@ __global__ __launch_bounds__(kBlock) void k_bicg_update(const BlockEnt *tab, con
   if (skip_inner(in, st)) return;
   const Walk wk = make_walk(in, e.lb);
   BicgUpdate<T> f;
-  f.p = (const T *)in.p[st->pcur];
-  f.s = (const T *)in.bs[2];
-  f.t = (const T *)in.bs[3];
-  f.rhat = (const T *)in.bs[0];
-  f.res = (T *)in.res;
-  f.d = (T *)in.d;
+  f.p = gp<T>(in.p[st->pcur]);
+  f.s = gp<T>(in.bs[2]);
+  f.t = gp<T>(in.bs[3]);
+  f.rhat = gp<T>(in.bs[0]);
+  f.res = gp<T>(in.res);
+  f.d = gp<T>(in.d);
   f.alpha = (T)st->alpha;
   f.omega = (T)st->omega;
   f.first = st->inner == 0;
   f.acc = 0.0;
-  stream(in, wk, f);
+  stream(wk, f);
   double acc[1] = {f.acc};
   publish<1>(in, part, e.lb, acc);
 }
@@ -592,8 +648,8 @@ __global__ __launch_bounds__(kBlock) void k_copy_res(const BlockEnt *tab, const 
   const T *res = (const T *)in.res;
   T *rhat = (T *)in.bs[0];
   if (wk.act) {
-    int64_t c = wk.base + (int64_t)wk.m0 * in.sm;
-    for (int m = wk.m0; m < wk.m1; ++m, c += in.sm) rhat[c] = res[c];
+    int64_t c = wk.base + (int64_t)wk.m0 * wk.sm;
+    for (int m = wk.m0; m < wk.m1; ++m, c += wk.sm) rhat[c] = res[c];
   }
 }
 
@@ -620,9 +676,9 @@ __global__ __launch_bounds__(kBlock) void k_gauge_sum(const BlockEnt *tab, const
   const Walk wk = make_walk(in, e.lb);
   double acc[1] = {0.0};
   if (wk.act) {
-    int64_t c = wk.base + (int64_t)wk.m0 * in.sm;
-    for (int m = wk.m0; m < wk.m1; ++m, c += in.sm)
-      if (in.code[c] & kValidBit) acc[0] += P[c];
+    int64_t c = wk.base + (int64_t)wk.m0 * wk.sm;
+    for (int m = wk.m0; m < wk.m1; ++m, c += wk.sm)
+      if (wk.code[c] & kValidBit) acc[0] += P[c];
   }
   publish<1>(in, part, e.lb, acc);
 }
@@ -648,10 +704,10 @@ __global__ __launch_bounds__(kBlock) void k_gauge_apply(const BlockEnt *tab, con
   const bool zero = st->normS2 == 0.0;
   const double mean1 = st->red[0] * in.inv_nvalid;
   if (wk.act) {
-    int64_t c = wk.base + (int64_t)wk.m0 * in.sm;
-    for (int m = wk.m0; m < wk.m1; ++m, c += in.sm) {
+    int64_t c = wk.base + (int64_t)wk.m0 * wk.sm;
+    for (int m = wk.m0; m < wk.m1; ++m, c += wk.sm) {
       T v;
-      if (in.code[c] & kValidBit) {
+      if (wk.code[c] & kValidBit) {
         if (zero) {
           v = T(0);
         } else if (in.ncomp > 1) {
@@ -688,10 +744,15 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
   }
   __shared__ double lds[kWavesPerBlock * 4];
   double s[4] = {0.0, 0.0, 0.0, 0.0};
+  // slots are 32 bytes: load them as double2 pairs, several rounds in flight
+  const double2 *slots = reinterpret_cast<const double2 *>(part + (int64_t)in.part_base * 4);
+#pragma unroll 8
   for (int i = threadIdx.x; i < in.nblocks; i += kBlock) {
-    const double *slot = part + ((int64_t)in.part_base + i) * 4;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) s[k] += slot[k];
+    const double2 a = slots[2 * i], b = slots[2 * i + 1];
+    s[0] += a.x;
+    s[1] += a.y;
+    s[2] += b.x;
+    s[3] += b.y;
   }
   block_sum<4>(s, lds);
   if (threadIdx.x != 0) return;
@@ -723,6 +784,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
         st->rr = s[1];
         st->inner = 0;
         st->first = 1;
+        st->beta = 0.0;  // the first search direction is the residual itself
         st->have_delta = 1;
         // BiCGStab restarts with the new residual as its shadow vector
         st->rho = s[1];
@@ -770,13 +832,18 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
 // ---------------------------------------------------------------------------
 template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Inst *insts, State *sts, double *part,
-                                                  int op, const T *x, T *y) {
+                                                  int op, const T *x_, T *y_) {
   PI_PROLOGUE
+  const PI_G T *x = gp<T>(x_);
+  PI_G T *y = gp<T>(y_);
   __shared__ T lut_a[6][kStates];
   __shared__ T lut_b[6][kStates];
   load_lut<T>(in.lut_np1, lut_a);
   load_lut<T>(in.lut_n, lut_b);
   const Walk wk = make_walk(in, e.lb);
+  T a[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) a[d] = (T)in.a[d];
   const int bits = dir_bits(ND);
   auto load = [&](int64_t c) -> T { return x[c]; };
   auto body = [&](int64_t c, const Plane<T, int> &pl, T vW, T vE, T vP, T vN) -> T {
@@ -809,7 +876,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Ins
         const int t = dstate(cd, d, bits);
         if (t) {
           s += lut_b[d][t] * nb[d];
-          wc -= (T)in.a[d];
+          wc -= a[d];
         }
       }
       s += wc * vC;
@@ -817,13 +884,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Ins
       s = T(0);
       for (int d = 0; d < 2 * ND; ++d) {
         const int t = dstate(cd, d, bits);
-        if (t) s += (T)in.a[d] * (vC - nb[d]);
+        if (t) s += a[d] * (vC - nb[d]);
       }
     }
     return s;
   };
   auto store = [&](int64_t c, const T &v) { y[c] = v; };
-  march<ND, T, int, T>(in, wk, load, [](int64_t) { return 0; }, body, store);
+  march<ND, T, int, T>(wk, load, [](int64_t) { return 0; }, body, store);
 }
 
 // ---------------------------------------------------------------------------

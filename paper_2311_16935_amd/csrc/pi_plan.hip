@@ -265,9 +265,9 @@ void set_walk(Inst &in, int ndim, const int64_t dims[3], int mseg_override) {
   }
   int mseg = mseg_override;
   if (mseg <= 0) {
-    // about two occupancy rounds of waves (8 per SIMD on 256 CUs), with
+    // about one occupancy round of waves (8 per SIMD on 256 CUs), with
     // segments a multiple of the streaming depth
-    const int64_t target_waves = 16384;
+    const int64_t target_waves = 8192;
     const int64_t nseg_t = std::max<int64_t>(1, target_waves / std::max<int64_t>(1, strips));
     const int step = kStream;
     mseg = (int)std::max<int64_t>(step, (in.nm + nseg_t - 1) / nseg_t);
