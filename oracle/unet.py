@@ -97,3 +97,44 @@ def mse(pred, target, mask):
     cnt = m.sum()
     d = (pred - target) * m
     return float((d * d).sum() / cnt), 2.0 * d / cnt
+
+
+def adam(w, g, m, v, lr, beta1, beta2, eps, step):
+    """One Adam step (Kingma and Ba, Algorithm 1) with bias-corrected moments;
+    returns the new (w, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    return w - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def block_mean(fields, mask, factor):
+    """Network input from solver-grid fields (storage order [z, y, x] or
+    [y, x]): per factor-sized block, the mean of each field over the block's
+    data cells (0 if none) and the fraction of data cells."""
+    nd = fields[0].ndim
+    m = np.ones(fields[0].shape, bool) if mask is None else np.asarray(mask, bool)
+    cshape = tuple(s // factor for s in fields[0].shape)
+    out = np.zeros(cshape + (len(fields) + 1,))
+    for idx in np.ndindex(*cshape):
+        sl = tuple(slice(i * factor, (i + 1) * factor) for i in idx)
+        mb = m[sl]
+        cnt = mb.sum()
+        for k, f in enumerate(fields):
+            out[idx + (k,)] = f[sl][mb].sum() / cnt if cnt else 0.0
+        out[idx + (len(fields),)] = cnt / factor ** nd
+    return out
+
+
+def upsample_linear(coarse, factor):
+    """Cell-centred multilinear interpolation of a coarse field onto a grid
+    `factor` times finer along every axis, constant beyond the outermost
+    coarse centres; one 1-D linear interpolation (numpy.interp) per axis."""
+    out = np.asarray(coarse, float)
+    for ax in range(out.ndim):
+        n = out.shape[ax]
+        xc = np.arange(n, dtype=float)
+        xf = (np.arange(n * factor) + 0.5) / factor - 0.5
+        out = np.apply_along_axis(lambda v: np.interp(xf, xc, v), ax, out)
+    return out

@@ -9,14 +9,16 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = ["include/pi.h"]
-LIBS = {"include/pi.h": "paper_2311_16935_amd/libpi.so"}
+HEADERS = ["include/pi.h", "include/pi_unet.h"]
+LIBS = {"include/pi.h": "paper_2311_16935_amd/libpi.so", "include/pi_unet.h": "paper_2311_16935_amd/libpi.so"}
+PREFIX = {"include/pi.h": "pi", "include/pi_unet.h": "pu"}
 
 
 def declared(header):
     txt = open(os.path.join(ROOT, header)).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(pi\w*)\s*\(", txt, flags=re.M)
+    pre = PREFIX[header]
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(" + pre + r"_\w*)\s*\(", txt, flags=re.M)
     return sorted(set(names))
 
 
@@ -30,7 +32,7 @@ def test_library_exports_every_declared_function(header):
     for n in names:
         assert hasattr(lib, n), n
     out = subprocess.run(["nm", "-D", "--defined-only", lib_path], capture_output=True, text=True).stdout
-    exported = set(re.findall(r"\bT (pi\w+)", out))
+    exported = set(re.findall(r"\bT (p[iu]_\w+)", out))
     assert set(names) <= exported
 
 
@@ -41,6 +43,15 @@ def test_binding_names_match_header():
     assert sorted(pi.EXPORTED) == names
     for n in names:
         assert callable(getattr(pi, n))
+
+
+def test_layer_binding_names_match_header():
+    from paper_2311_16935_amd import unet
+
+    names = declared("include/pi_unet.h")
+    assert sorted(unet.EXPORTED) == names
+    for n in names:
+        assert callable(getattr(unet, n))
 
 
 def test_status_strings_without_gpu():

@@ -89,3 +89,48 @@ def test_upconv_pool_head_backward_match_finite_differences():
         assert gxh[i] == pytest.approx(v, rel=1e-6, abs=1e-9)
     for i, v in _fd(lh, w, idx=[(0,), (3,)]).items():
         assert gw[i] == pytest.approx(v, rel=1e-6, abs=1e-9)
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    """With zero moments, the bias-corrected first step is lr * g / (|g| + eps)."""
+    rng = np.random.default_rng(3)
+    w = rng.normal(size=20)
+    g = rng.normal(size=20)
+    w1, m1, v1 = U.adam(w, g, np.zeros(20), np.zeros(20), 1e-2, 0.9, 0.999, 1e-12, 1)
+    assert np.allclose(w - w1, 1e-2 * np.sign(g), atol=1e-12)
+    assert np.allclose(m1, 0.1 * g) and np.allclose(v1, 1e-3 * g * g)
+    # a constant gradient keeps the corrected step at lr * sign(g) for every step
+    w2, m2, v2 = U.adam(w1, g, m1, v1, 1e-2, 0.9, 0.999, 1e-12, 2)
+    assert np.allclose(w1 - w2, 1e-2 * np.sign(g), atol=1e-10)
+
+
+def test_block_mean_against_loops_and_invariants():
+    rng = np.random.default_rng(4)
+    f = rng.normal(size=(4, 6, 8))
+    mask = rng.uniform(size=f.shape) > 0.3
+    out = U.block_mean([f, 2 * f], mask, 2)
+    z, y, x = 1, 2, 3
+    vals = [f[2 * z + a, 2 * y + b, 2 * x + c] for a in (0, 1) for b in (0, 1) for c in (0, 1)
+            if mask[2 * z + a, 2 * y + b, 2 * x + c]]
+    assert out[z, y, x, 0] == pytest.approx(np.mean(vals))
+    assert out[z, y, x, 1] == pytest.approx(2 * np.mean(vals))
+    assert out[z, y, x, 2] == pytest.approx(len(vals) / 8)
+    # full mask: the data-weighted mean over all blocks is the global mean
+    full = U.block_mean([f], None, 2)
+    assert full[..., 0].mean() == pytest.approx(f.mean())
+    assert np.all(full[..., 1] == 1.0)
+
+
+def test_upsample_is_exact_on_linear_fields_inside_and_constant_outside():
+    cz, cy, cx = np.meshgrid(np.arange(3.0), np.arange(4.0), np.arange(5.0), indexing="ij")
+    coarse = 0.5 + 2.0 * cx - 1.5 * cy + 0.25 * cz
+    f = 4
+    up = U.upsample_linear(coarse, f)
+    assert up.shape == (12, 16, 20)
+    for (k, j, i) in [(5, 7, 9), (4, 2, 17), (6, 13, 3)]:
+        u = [(v + 0.5) / f - 0.5 for v in (k, j, i)]
+        assert up[k, j, i] == pytest.approx(0.5 + 2.0 * u[2] - 1.5 * u[1] + 0.25 * u[0], abs=1e-12)
+    # beyond the outermost centres the field is held constant
+    assert up[0, 0, 0] == pytest.approx(coarse[0, 0, 0])
+    assert up[-1, -1, -1] == pytest.approx(coarse[-1, -1, -1])
+    assert np.allclose(U.upsample_linear(np.full((2, 3), 7.0), 3), 7.0)
