@@ -52,6 +52,11 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--mode", choices=("solve", "kernels"), default="solve",
                     help="kernels: only time the outer-step kernels and a copy of known size (for counters)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the size-based default tile")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2311_16935_amd", "weights",
+                                                      "unet_blobs64.safetensors"),
+                    help="trained warm-start network; the warm-started solve is skipped if missing")
+    ap.add_argument("--no-warm", action="store_true")
     return ap.parse_args()
 
 
@@ -144,6 +149,45 @@ def kernel_mode(args, pi, plan, grads, P, ncell):
                       "kernel_source_sha256": kernel_source_hash()}), flush=True)
 
 
+def warm_start_leg(args, pi, plan, grads, P_plain, n):
+    """The same solve from the learned guess: inference (gradient RMS, 4x
+    block means, U-Net, trilinear upsampling) plus the plain solver finishing
+    from the guess, timed end to end per solve; the converged field is
+    compared with the zero-start answer."""
+    import torch
+
+    from paper_2311_16935_amd.warmstart import UNet, WarmStart
+
+    net = UNet.from_file(args.weights)
+    factor = n // int(net.meta.get("train_n", 64))
+    ws = WarmStart(net, factor)
+    P = torch.empty_like(P_plain)
+    for i in range(args.warmup):
+        r = ws.solve(plan, grads, P=P, tol=args.tol)
+        progress(f"warm-start warmup {i}: {r.info['outer_iters']} outer steps")
+    torch.cuda.synchronize()
+    infos, t_guess = [], 0.0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        a = time.perf_counter()
+        ws.guess(plan, grads, P)
+        torch.cuda.synchronize()
+        t_guess += time.perf_counter() - a
+        r = plan.solve(grads, P=P, tol=args.tol, warm_start=True)
+        infos.append(r.info)
+        progress(f"warm-start step {i}: {r.info['outer_iters']} outer steps")
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / max(1, args.steps)
+    info = infos[-1]
+    assert info["status"] == 0 and info["eps_R"] <= args.tol, info
+    rms = float(P_plain.double().pow(2).mean().sqrt())
+    diff = float((P.double() - P_plain.double()).abs().max()) / rms
+    return {"s_per_solve": sec, "guess_s": t_guess / max(1, args.steps), "outer_iters": info["outer_iters"],
+            "inner_iters": info["inner_iters_total"], "eps_R": info["eps_R"], "factor": factor,
+            "weights": os.path.relpath(args.weights, ROOT), "train": {k: net.meta[k] for k in net.meta},
+            "maxabs_vs_plain_rel_rms": diff}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -167,6 +211,12 @@ def main():
     if args.mode == "kernels":
         kernel_mode(args, pi, plan, grads, P, ncell)
         return
+    tune = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        m = plan.autotune(reps=5)
+        tune = {"mseg": m, "seconds": time.perf_counter() - t0}
+        progress(f"autotuned tile: {m} planes per segment ({tune['seconds']:.1f} s, outside the timed region)")
     for i in range(args.warmup):
         r = plan.solve(grads, P=P, tol=args.tol)
         progress(f"warmup {i}: {r.info['ms'] / 1e3:.2f} s, {r.info['outer_iters']} outer steps")
@@ -182,6 +232,10 @@ def main():
     sec = elapsed / max(1, args.steps)
     info = infos[-1]
     assert info["status"] == 0 and info["eps_R"] <= args.tol, info
+    P_plain = P.clone()
+    warm = None
+    if not args.no_warm and os.path.exists(args.weights):
+        warm = warm_start_leg(args, pi, plan, grads, P_plain, n)
 
     # kernel durations, measured with HIP events on the library's stream
     src_hash = kernel_source_hash()
@@ -224,6 +278,8 @@ def main():
                   "eps_R": info["eps_R"], "eps_P": info["eps_P"],
                   "outer_point_iters_per_s": ncell * info["outer_iters"] / sec,
                   "inner_point_iters_per_s": ncell * info["inner_iters_total"] / sec},
+        "warm_start": warm,
+        "autotune": tune,
         "roofline": roof,
         "kernels": kern,
         "kernel_source_sha256": src_hash,

@@ -193,6 +193,19 @@ pi_status pi_apply(pi_plan_t plan, int op, const void *x, void *y, void *stream)
 #define PI_K_UPDATE 2  /* inner correction and residual update                 */
 pi_status pi_time_kernel(pi_plan_t plan, int kernel, int32_t reps, double *avg_ms, void *stream);
 
+/*
+ * pi_autotune -- pick the tile (pi_set_tile) that minimises the time of one
+ * outer step of Algorithm 1 for this plan: for each candidate segment length
+ * it times the outer kernel once and the inner kernels `inner_iters` times
+ * (pi_time_kernel, `reps` launches each) and keeps the fastest.  Results are
+ * cached per (ndim, dims, precision, inner solver) for the life of the process,
+ * so later plans of the same shape take the cached tile without timing.  The
+ * chosen segment length is returned in *mseg (may be NULL).  Overwrites the
+ * plan's workspace; synchronous.  The paper has no counterpart (its kernels
+ * use one fixed launch shape); the knob changes speed, never results.
+ */
+pi_status pi_autotune(pi_plan_t plan, int32_t reps, int32_t *mseg, void *stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *pi_status_string(pi_status status);
 

@@ -82,6 +82,8 @@ def _load():
     lib.pi_get_tile.restype = ctypes.c_int32
     lib.pi_time_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(dbl), vp]
     lib.pi_time_kernel.restype = ctypes.c_int
+    lib.pi_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.pi_autotune.restype = ctypes.c_int
     lib.pi_status_string.argtypes = [ctypes.c_int]
     lib.pi_status_string.restype = ctypes.c_char_p
     return lib
@@ -91,7 +93,7 @@ lib = _load()
 
 EXPORTED = ("pi_plan", "pi_plan_destroy", "pi_workspace_bytes", "pi_set_inner_iters", "pi_set_tile",
             "pi_get_tile", "pi_solve",
-            "pi_solve_batched", "pi_source", "pi_apply", "pi_time_kernel", "pi_status_string")
+            "pi_solve_batched", "pi_source", "pi_apply", "pi_time_kernel", "pi_autotune", "pi_status_string")
 
 PI_K_OUTER, PI_K_SPMV, PI_K_UPDATE = 0, 1, 2
 
@@ -192,6 +194,14 @@ def pi_time_kernel(plan, kernel, reps, stream=None) -> float:
     return ms.value
 
 
+def pi_autotune(plan, reps=5, stream=None) -> int:
+    m = ctypes.c_int32()
+    rc = lib.pi_autotune(plan, int(reps), ctypes.byref(m), _stream(stream))
+    if rc != PI_OK:
+        raise PiError(rc, "pi_autotune")
+    return m.value
+
+
 # ---------------------------------------------------------------------------
 # convenience layer over the same calls
 # ---------------------------------------------------------------------------
@@ -227,6 +237,10 @@ class Plan:
 
     def set_inner_iters(self, k):
         pi_set_inner_iters(self.handle, k)
+
+    def autotune(self, reps=5, stream=None):
+        """Pick and set the fastest tile for this grid (cached per shape)."""
+        return pi_autotune(self.handle, reps, stream)
 
     def _check(self, t, name):
         if t is None:

@@ -12,7 +12,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "pi_kernels.h"
@@ -411,6 +414,48 @@ out:
   if (a) (void)hipEventDestroy(a);
   if (b) (void)hipEventDestroy(b);
   (void)hipStreamSynchronize(stream);
+  return rc;
+}
+
+// tile cache of pi_autotune: (ndim, nx, ny, nz, fp64, bicgstab) -> mseg
+static std::mutex g_tune_mu;
+static std::map<std::array<int64_t, 6>, int32_t> g_tune;
+
+extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, void *stream) {
+  if (!p || reps < 1) return PI_ERR_INVALID_ARG;
+  const std::array<int64_t, 6> key = {p->ndim, p->dims[0], p->dims[1], p->dims[2], p->fp64, p->bicgstab};
+  int32_t best = -1;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) best = it->second;
+  }
+  if (best < 0) {
+    pi_status rc = pi_set_tile(p, 0);
+    if (rc != PI_OK) return rc;
+    std::vector<int32_t> cand = {p->inst.mseg};
+    for (int32_t m = kStream; m <= 256; m *= 2)
+      if (m < p->inst.nm && std::find(cand.begin(), cand.end(), m) == cand.end()) cand.push_back(m);
+    double best_ms = 1e300;
+    for (int32_t m : cand) {
+      rc = pi_set_tile(p, m);
+      if (rc != PI_OK) return rc;
+      double t_outer = 0.0, t_spmv = 0.0, t_upd = 0.0;
+      if ((rc = pi_time_kernel(p, PI_K_OUTER, reps, &t_outer, stream)) != PI_OK ||
+          (rc = pi_time_kernel(p, PI_K_SPMV, reps, &t_spmv, stream)) != PI_OK ||
+          (rc = pi_time_kernel(p, PI_K_UPDATE, reps, &t_upd, stream)) != PI_OK)
+        return rc;
+      const double step = t_outer + p->inner_iters * (t_spmv + t_upd);
+      if (step < best_ms) {
+        best_ms = step;
+        best = p->inst.mseg;
+      }
+    }
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[key] = best;
+  }
+  pi_status rc = pi_set_tile(p, best);
+  if (rc == PI_OK && mseg_out) *mseg_out = p->inst.mseg;
   return rc;
 }
 

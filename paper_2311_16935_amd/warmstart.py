@@ -31,7 +31,7 @@ from dataclasses import dataclass
 
 import torch
 
-from . import PI_OK, PI_ERR_NOT_CONVERGED, PiError, Plan, solve_batched
+from . import Plan, solve_batched
 from . import unet as U
 
 TAPS3 = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
@@ -61,10 +61,12 @@ def _align(n, a=64):
 
 
 class UNet:
-    def __init__(self, base=32, levels=4, cin=4, device="cuda:0", seed=0):
-        self.base, self.levels, self.cin, self.device = base, levels, cin, torch.device(device)
-        self.ch = [base << l for l in range(levels)]
-        self.layers = {}
+    @staticmethod
+    def layout(base=32, levels=4, cin=4):
+        """Layers in call order and their slices of the flat parameter buffer
+        (every slice starts on a 64-element boundary); returns (layers, size)."""
+        ch = [base << l for l in range(levels)]
+        layers = {}
         off = 0
 
         def add(name, kind, ci, co, taps, bias=True):
@@ -75,16 +77,22 @@ class UNet:
             if bias:
                 ob = off
                 off = _align(off + co)
-            self.layers[name] = Layer(name, kind, ci, co, taps, ow, ob)
+            layers[name] = Layer(name, kind, ci, co, taps, ow, ob)
 
         for l in range(levels):
-            add(f"enc{l}a", "conv", cin if l == 0 else self.ch[l - 1], self.ch[l], 27)
-            add(f"enc{l}b", "conv", self.ch[l], self.ch[l], 27)
+            add(f"enc{l}a", "conv", cin if l == 0 else ch[l - 1], ch[l], 27)
+            add(f"enc{l}b", "conv", ch[l], ch[l], 27)
         for l in reversed(range(levels - 1)):
-            add(f"up{l}", "up", self.ch[l + 1], self.ch[l], 8, bias=False)
-            add(f"dec{l}a", "conv", 2 * self.ch[l], self.ch[l], 27)
-            add(f"dec{l}b", "conv", self.ch[l], self.ch[l], 27)
-        add("head", "head", self.ch[0], 1, 1)
+            add(f"up{l}", "up", ch[l + 1], ch[l], 8, bias=False)
+            add(f"dec{l}a", "conv", 2 * ch[l], ch[l], 27)
+            add(f"dec{l}b", "conv", ch[l], ch[l], 27)
+        add("head", "head", ch[0], 1, 1)
+        return layers, off
+
+    def __init__(self, base=32, levels=4, cin=4, device="cuda:0", seed=0):
+        self.base, self.levels, self.cin, self.device = base, levels, cin, torch.device(device)
+        self.ch = [base << l for l in range(levels)]
+        self.layers, off = self.layout(base, levels, cin)
         self.nparams = off
         dev = self.device
         self.master = torch.zeros(off, dtype=torch.float32, device=dev)
@@ -331,16 +339,15 @@ def make_dataset(n, count, seed_base, tol=1e-6, chunk=32, device="cuda:0", noise
     stats = []
     rms = torch.zeros(1, dtype=torch.float32, device=device)
     small = torch.zeros(U.RMS_WORK_FLOATS, dtype=torch.float32, device=device)
-    plan = None
+    pool = []  # one plan (and so one workspace) per instance of a batch
     t0 = time.time()
     for c0 in range(0, count, chunk):
         ids = list(range(c0, min(count, c0 + chunk)))
         works = [synth.config_blobs_3d(n, noise=noise, seed=seed_base + i, device=device) for i in ids]
         grads = [[g.float().contiguous() for g in w.grads] for w in works]
-        if plan is None:
-            plan = Plan(works[0].dims, works[0].spacing)
-        plans = [plan] * len(ids)
-        rc, Ps, infos = solve_batched(plans, grads, tol=tol, max_iter=200000)
+        while len(pool) < len(ids):
+            pool.append(Plan(works[0].dims, works[0].spacing))
+        rc, Ps, infos = solve_batched(pool[:len(ids)], grads, tol=tol, max_iter=200000)
         for k, i in enumerate(ids):
             g = grads[k]
             U.pu_grad_rms(g[0], g[1], g[2], None, n ** 3, rms, small)
@@ -353,12 +360,42 @@ def make_dataset(n, count, seed_base, tol=1e-6, chunk=32, device="cuda:0", noise
             log(f"dataset {ids[-1] + 1}/{count} solves ({time.time() - t0:.1f}s, "
                 f"outer {infos[0]['outer_iters']}, eps_R {infos[0]['eps_R']:.2e})")
     torch.cuda.synchronize()
-    plan.close()
+    for p in pool:
+        p.close()
     return x, tgt, stats
 
 
-def train(net: UNet, x, tgt, steps, batch=4, lr=1e-3, seed=0, log=None, log_every=100):
-    """Adam on the mean squared error; cosine learning-rate decay."""
+_CH_OF_AXIS = (2, 1, 0)  # grid axes (z, y, x) -> gradient channel
+
+
+def _symmetry(x, t, gen):
+    """A random element of the cube's symmetry group applied to a batch:
+    axis permutation and reflections of the grid, with the gradient
+    components permuted and negated alongside (the pressure is a scalar and
+    only moves).  The method is equivariant under these maps on isotropic
+    cubic grids, so every training pair yields 48."""
+    perm = torch.randperm(3, generator=gen).tolist()
+    flips = [bool(torch.randint(0, 2, (1,), generator=gen).item()) for _ in range(3)]
+    x = x.permute(0, 1 + perm[0], 1 + perm[1], 1 + perm[2], 4)
+    t = t.permute(0, 1 + perm[0], 1 + perm[1], 1 + perm[2])
+    idx = [0, 0, 0, 3]
+    for k in range(3):
+        idx[_CH_OF_AXIS[k]] = _CH_OF_AXIS[perm[k]]
+    x = x[..., idx]
+    dims = [1 + k for k in range(3) if flips[k]]
+    if dims:
+        x, t = x.flip(dims), t.flip(dims)
+        sign = torch.ones(4, dtype=x.dtype, device=x.device)
+        for k in range(3):
+            if flips[k]:
+                sign[_CH_OF_AXIS[k]] = -1
+        x = x * sign
+    return x, t
+
+
+def train(net: UNet, x, tgt, steps, batch=4, lr=1e-3, seed=0, log=None, log_every=100, augment=True):
+    """Adam on the mean squared error; cosine learning-rate decay; random
+    cube symmetries of the training pairs (cubic grids)."""
     count = x.shape[0]
     res = tuple(x.shape[1:4])
     B = net.buffers(batch, res)
@@ -366,10 +403,14 @@ def train(net: UNet, x, tgt, steps, batch=4, lr=1e-3, seed=0, log=None, log_ever
     t0 = time.time()
     hist = []
     target = torch.empty((batch,) + res, dtype=torch.float32, device=x.device)
+    cubic = res[0] == res[1] == res[2]
     for s in range(steps):
         idx = torch.randint(0, count, (batch,), generator=g).to(x.device)
-        torch.index_select(x, 0, idx, out=B["x0"])
-        torch.index_select(tgt, 0, idx, out=target)
+        xb, tb = x.index_select(0, idx), tgt.index_select(0, idx)
+        if augment and cubic:
+            xb, tb = _symmetry(xb, tb, g)
+        B["x0"].copy_(xb)
+        target.copy_(tb)
         lr_s = lr * 0.5 * (1.0 + math.cos(math.pi * s / max(1, steps)))
         net.train_step(B, target, lr_s)
         if log and (s % log_every == 0 or s == steps - 1):

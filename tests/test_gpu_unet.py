@@ -6,8 +6,10 @@ the oracle sees exactly the kernels' operands.  Bars: FP32 outputs within
 2e-5 of the largest reference magnitude (FP32 accumulation over at most a
 few thousand products); BF16 outputs additionally within one BF16 rounding
 (2^-8 relative).  The whole-network gradient check composes the oracle's
-layers in FP64 while the device keeps BF16 activations between layers, so
-it compares each parameter gradient in relative L2 norm (bar 5e-2).
+layers in FP64, rounding to BF16 wherever the device stores an activation
+or its gradient in BF16, and compares each parameter gradient in relative L2
+norm (bar 1e-2: FP32 against FP64 accumulation, and the rare value that
+lands on the other side of a BF16 rounding or ReLU boundary).
 """
 
 import math
@@ -99,9 +101,10 @@ def test_conv3_backward(cin, cout):
     gy = _bf(rng.normal(size=shape + (cout,)))
     rgx, rgW, rgb = O.conv3_backward(x, W, gy)
     xd, wd, gyd = _dev_bf(x), _dev_bf(W), _dev_bf(gy)
-    wt = torch.empty_like(wd)
+    wt = torch.empty((27, cout, cin), dtype=torch.bfloat16, device=DEV)
     U.pu_transpose_taps(wd, wt, 27, cin, cout)
-    assert torch.equal(wt.cpu(), wd.cpu().permute(0, 2, 1).contiguous())
+    same = bool(torch.equal(wt.cpu(), wd.cpu().permute(0, 2, 1).contiguous()))
+    assert same, 'per-tap transpose differs'
     if cin % 8 == 0:
         gx = torch.zeros(shape + (cin,), dtype=torch.float32, device=DEV)
         U.pu_conv(U.tensor(gyd), wt, 27, NEG3, None, U.tensor(gx), shape[1:], y_fp32=True)
@@ -131,8 +134,8 @@ def test_wgrad_splits_many_chunks():
     work = torch.zeros(U.pu_wgrad_work_floats(27, cin, cout, npos), dtype=torch.float32, device=DEV)
     dW = torch.zeros((27, cin, cout), dtype=torch.float32, device=DEV)
     db = torch.zeros(cout, dtype=torch.float32, device=DEV)
-    U.pu_conv_wgrad(U.tensor(_dev_bf(x)), U.tensor(_dev_bf(gy)), 27, TAPS3, dW, db, shape[1:], 1, 1, (0, 0, 0),
-                    work)
+    xd, gyd = _dev_bf(x), _dev_bf(gy)  # descriptors hold raw pointers: keep the tensors alive
+    U.pu_conv_wgrad(U.tensor(xd), U.tensor(gyd), 27, TAPS3, dW, db, shape[1:], 1, 1, (0, 0, 0), work)
     _check(_host(dW), rgW, False, "wgrad")
     _check(_host(db), rgb, False, "bias grad")
 
@@ -155,7 +158,7 @@ def test_upconv_forward_backward():
     for q, oo in enumerate(UP8):
         U.pu_conv(U.tensor(xd), wd[q], 1, [(0, 0, 0)], None, U.tensor(y), shape[1:], 1, 2, oo, y_fp32=True)
     _check(_host(y), ref, False, "upconv fwd")
-    wt = torch.empty_like(wd)
+    wt = torch.empty((8, cout, cin), dtype=torch.bfloat16, device=DEV)
     U.pu_transpose_taps(wd, wt, 8, cin, cout)
     gx = torch.zeros(shape + (cin,), dtype=torch.float32, device=DEV)
     U.pu_conv(U.tensor(gyd), wt, 8, UP8, None, U.tensor(gx), shape[1:], 2, 1, (0, 0, 0), y_fp32=True)
@@ -223,7 +226,7 @@ def test_pool_relu_head_mse_adam():
         U.pu_adam(wd, _dev_f(gr), md, vd, wb, n, 1e-2, 0.9, 0.999, 1e-8, step)
         rw, rm, rv = O.adam(rw, gr, rm, rv, 1e-2, 0.9, 0.999, 1e-8, step)
     assert np.abs(_host(wd) - rw).max() <= 1e-6
-    assert np.array_equal(wb.cpu(), wd.cpu().to(torch.bfloat16))
+    assert bool(torch.equal(wb.cpu(), wd.cpu().to(torch.bfloat16))), 'bf16 copy differs'
 
 
 def test_prepare_input_upsample_and_rms():
@@ -258,25 +261,27 @@ def test_prepare_input_upsample_and_rms():
 
 
 # ------------------------------------------------------------ whole network
-def _oracle_network(P, x, target, levels, ch):
+def _oracle_network(P, x, target, levels, ch, q=lambda a: a):
     """FP64 forward and backward of the U-Net composed from the layer oracle;
-    P maps layer name -> (W, b).  Returns loss and name -> (gW, gb)."""
+    P maps layer name -> (W, b).  q is applied wherever the device stores a
+    tensor (activations and their gradients are kept in BF16 there), so the
+    comparison isolates the kernels' arithmetic from the storage format.
+    Returns loss and name -> (gW, gb)."""
     top = levels - 1
-    relu_mask = {}
     acts = {}
     h = x
     for l in range(levels):
-        a = O.conv3(h, *P[f"enc{l}a"], relu=True)
-        e = O.conv3(a, *P[f"enc{l}b"], relu=True)
+        a = q(O.conv3(h, *P[f"enc{l}a"], relu=True))
+        e = q(O.conv3(a, *P[f"enc{l}b"], relu=True))
         acts[f"in{l}"], acts[f"t{l}"], acts[f"e{l}"] = h, a, e
         if l < top:
-            h = O.pool(e)
+            h = q(O.pool(e))
     u = acts[f"e{top}"]
     for l in reversed(range(top)):
-        up = O.upconv(u, P[f"up{l}"][0], np.zeros(ch[l]))
+        up = q(O.upconv(u, P[f"up{l}"][0], np.zeros(ch[l])))
         cat = np.concatenate([up, acts[f"e{l}"]], axis=-1)
-        ua = O.conv3(cat, *P[f"dec{l}a"], relu=True)
-        ub = O.conv3(ua, *P[f"dec{l}b"], relu=True)
+        ua = q(O.conv3(cat, *P[f"dec{l}a"], relu=True))
+        ub = q(O.conv3(ua, *P[f"dec{l}b"], relu=True))
         acts[f"u{l}"], acts[f"cat{l}"], acts[f"ua{l}"], acts[f"ub{l}"] = u, cat, ua, ub
         u = ub
     y = O.head(u, P["head"][0][0, :, 0], P["head"][1][0])
@@ -284,28 +289,29 @@ def _oracle_network(P, x, target, levels, ch):
     G = {}
     gx, gw, gb = O.head_backward(u, P["head"][0][0, :, 0], gy)
     G["head"] = (gw, np.array([gb]))
-    g = gx
+    g = q(gx)
     for l in range(top):
         g = g * (acts[f"ub{l}"] > 0)
         gin, gW, gB = O.conv3_backward(acts[f"ua{l}"], P[f"dec{l}b"][0], g)
         G[f"dec{l}b"] = (gW, gB)
-        g = gin * (acts[f"ua{l}"] > 0)
+        g = q(gin) * (acts[f"ua{l}"] > 0)
         gcat, gW, gB = O.conv3_backward(acts[f"cat{l}"], P[f"dec{l}a"][0], g)
         G[f"dec{l}a"] = (gW, gB)
+        gcat = q(gcat)
         acts[f"gskip{l}"] = gcat[..., ch[l]:]
         gu, gW, _ = O.upconv_backward(acts[f"u{l}"], P[f"up{l}"][0], gcat[..., :ch[l]])
         G[f"up{l}"] = (gW, None)
-        g = gu
+        g = q(gu)
     for l in reversed(range(levels)):
         if l < top:
-            g = acts[f"gskip{l}"] + O.pool_backward(g)
+            g = q(acts[f"gskip{l}"] + O.pool_backward(g))
         g = g * (acts[f"e{l}"] > 0)
         gin, gW, gB = O.conv3_backward(acts[f"t{l}"], P[f"enc{l}b"][0], g)
         G[f"enc{l}b"] = (gW, gB)
-        g = gin * (acts[f"t{l}"] > 0)
+        g = q(gin) * (acts[f"t{l}"] > 0)
         gin, gW, gB = O.conv3_backward(acts[f"in{l}"], P[f"enc{l}a"][0], g)
         G[f"enc{l}a"] = (gW, gB)
-        g = gin
+        g = q(gin)
     return loss, G
 
 
@@ -330,22 +336,25 @@ def test_network_gradients_match_oracle_composition():
         W = src[L.off_w:L.off_w + L.wsize].reshape(L.taps, L.cin, L.cout)
         b = master[L.off_b:L.off_b + L.cout] if L.off_b >= 0 else None
         P[name] = (W, b)
-    rloss, RG = _oracle_network(P, x, target, levels, net.ch)
+    rloss, RG = _oracle_network(P, x, target, levels, net.ch, q=_bf)
     net.forward(B)
     U.pu_mse(B["y"], _dev_f(target), None, B["y"].numel(), net.loss, B["gy"], net.small)
     net.backward(B)
     torch.cuda.synchronize()
-    assert float(net.loss.item()) == pytest.approx(rloss, rel=2e-2)
+    assert float(net.loss.item()) == pytest.approx(rloss, rel=1e-3)
     grad = _host(net.grad)
+    errs = {}
     for name, L in net.layers.items():
         gW = grad[L.off_w:L.off_w + L.wsize].reshape(L.taps, L.cin, L.cout)
         rW, rb = RG[name]
-        e = np.linalg.norm(gW - rW) / np.linalg.norm(rW)
-        assert e <= 5e-2, f"{name} weight gradient rel L2 {e:.3e}"
+        rW = np.asarray(rW).reshape(gW.shape)
+        errs[name] = np.linalg.norm(gW - rW) / np.linalg.norm(rW)
         if rb is not None:
             gb = grad[L.off_b:L.off_b + L.cout]
-            e = np.linalg.norm(gb - rb) / np.linalg.norm(rb)
-            assert e <= 5e-2, f"{name} bias gradient rel L2 {e:.3e}"
+            errs[name + ".b"] = np.linalg.norm(gb - rb) / np.linalg.norm(rb)
+    print({k: f"{v:.2e}" for k, v in errs.items()})
+    bad = {k: v for k, v in errs.items() if not v <= 1e-2}
+    assert not bad, f"relative L2 gradient errors above 1e-2: {bad}"
 
 
 def test_training_reduces_loss_on_a_fixed_batch():

@@ -1,0 +1,43 @@
+"""The learned warm start: the committed network (trained on 64^3
+method-generated solves) must cut the outer iterations on held-out fields,
+and the solve that finishes from its guess must reach the same answer as the
+plain solve (the guess changes the trajectory, never the fixed point)."""
+
+import os
+
+import pytest
+import torch
+
+import synth
+from gpu_common import DEV, announce, requires_gpu
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2311_16935_amd",
+                       "weights", "unet_blobs64.safetensors")
+
+
+@pytest.mark.parametrize("seed", [90100, 90101])
+def test_trained_network_cuts_outer_iterations(seed):
+    import paper_2311_16935_amd as pi
+    from paper_2311_16935_amd.warmstart import UNet, WarmStart
+
+    announce("warm start", seed)
+    net = UNet.from_file(WEIGHTS, device=DEV)
+    ws = WarmStart(net, factor=1)
+    w = synth.config_blobs_3d(64, seed=seed, device=DEV)
+    g = [t.float().contiguous() for t in w.grads]
+    plan = pi.Plan(w.dims, w.spacing)
+    plain = plan.solve(g, tol=1e-8, max_iter=200000)
+    assert plain.status == pi.PI_OK
+    P0 = torch.empty_like(plain.P)
+    ws.guess(plan, g, P0)
+    guess_err = float(((P0 - P0.mean()) - plain.P).norm() / plain.P.norm())
+    warm = plan.solve(g, P=P0.clone(), tol=1e-8, max_iter=200000, warm_start=True)
+    assert warm.status == pi.PI_OK
+    print(f"outer: plain {plain.info['outer_iters']}, warm {warm.info['outer_iters']}; guess error {guess_err:.3f}")
+    assert guess_err < 0.2
+    assert warm.info["outer_iters"] < 0.9 * plain.info["outer_iters"]
+    rms = float(plain.P.double().pow(2).mean().sqrt())
+    assert float((warm.P.double() - plain.P.double()).abs().max()) <= 1e-5 * rms
+    plan.close()
