@@ -41,7 +41,7 @@ BYTES_PER_CELL = {
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="grid side (256 is the benchmark workload)")
     ap.add_argument("--tol", type=float, default=1e-6)
@@ -145,8 +145,8 @@ def kernel_mode(args, pi, plan, grads, P, ncell):
         torch.bitwise_not(x, out=y)
     torch.cuda.synchronize()
     res["bitwise_not"] = {"bytes_read": 4 * ncell, "bytes_written": 4 * ncell, "launches": args.kernel_reps}
-    print(json.dumps({"mode": "kernels", "n": args.n, "cells": ncell, "kernels": res,
-                      "kernel_source_sha256": kernel_source_hash()}), flush=True)
+    print(json.dumps({"mode": "kernels", "n": args.n, "cells": ncell, "tile": pi.pi_get_tile(plan.handle),
+                      "kernels": res, "kernel_source_sha256": kernel_source_hash()}), flush=True)
 
 
 def warm_start_leg(args, pi, plan, grads, P_plain, n):
@@ -208,15 +208,15 @@ def main():
     P = torch.empty((n, n, n), dtype=torch.float32, device=dev)
     ncell = n ** 3
     progress(f"plan ready: {n}^3, tile {pi.pi_get_tile(plan.handle)}, {plan.workspace_bytes / 2**30:.2f} GiB")
-    if args.mode == "kernels":
-        kernel_mode(args, pi, plan, grads, P, ncell)
-        return
     tune = None
     if not args.no_autotune:
         t0 = time.perf_counter()
         m = plan.autotune(reps=5)
         tune = {"mseg": m, "seconds": time.perf_counter() - t0}
         progress(f"autotuned tile: {m} planes per segment ({tune['seconds']:.1f} s, outside the timed region)")
+    if args.mode == "kernels":
+        kernel_mode(args, pi, plan, grads, P, ncell)
+        return
     for i in range(args.warmup):
         r = plan.solve(grads, P=P, tol=args.tol)
         progress(f"warmup {i}: {r.info['ms'] / 1e3:.2f} s, {r.info['outer_iters']} outer steps")
