@@ -30,10 +30,13 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 # algorithmic bytes per cell per launch (FP32 mode): what each kernel must read
-# and write once, neighbour re-reads excluded
+# and write once, neighbour re-reads excluded.  The benchmark grid has no
+# mask, so the stencil kernels derive the 4-byte counter code of each cell
+# from its coordinates instead of reading it (a masked grid adds 4 bytes to
+# the two stencil kernels).
 BYTES_PER_CELL = {
-    "k_outer": 8 + 4 + 8 + 4 + 8 + 4,   # P, delta, S (FP64), code in; P', r out
-    "k_cg_spmv": 4 + 4 + 4 + 4 + 4,     # r, p, code in; p', q out
+    "k_outer": 8 + 4 + 4 + 8 + 8 + 4,   # P, d, p (last CG step folded in), S (FP64) in; P', r out
+    "k_cg_spmv": 4 + 4 + 4 + 4,         # r, p in; p', q out
     "k_cg_update": 4 * 4 + 2 * 4,       # p, q, r, delta in; delta, r out
 }
 

@@ -109,12 +109,17 @@ size_t pi_workspace_bytes(pi_plan_t plan);
 pi_status pi_set_inner_iters(pi_plan_t plan, int32_t iters);
 
 /*
- * Tile shape: every wave marches `mseg` planes (3-D) or rows (2-D) of a
- * 64-cell strip; 0 restores the size-based default.  The autotuner sweeps
- * this knob.  pi_get_tile returns the current value.
+ * Tile shape of the stencil kernels: every wave owns a strip of 64 *
+ * lane_cells consecutive cells along x and marches `mseg` planes (3-D) or
+ * rows (2-D) along the slowest axis.  mseg 0 restores the size-based
+ * default.  lane_cells is 1 or 4 (4 needs nx % 4 == 0: each lane then moves
+ * its cells with 16-byte accesses), 0 picks 4 when allowed, else 1.  The
+ * autotuner sweeps both knobs.  Returns PI_ERR_INVALID_ARG for other values.
+ * pi_get_tile / pi_get_lane_cells return the current values.
  */
-pi_status pi_set_tile(pi_plan_t plan, int32_t mseg);
+pi_status pi_set_tile(pi_plan_t plan, int32_t mseg, int32_t lane_cells);
 int32_t pi_get_tile(pi_plan_t plan);
+int32_t pi_get_lane_cells(pi_plan_t plan);
 
 /*
  * pi_solve -- Algorithm 1 on one grid.
@@ -175,7 +180,9 @@ pi_status pi_source(pi_plan_t plan, const void *gx, const void *gy, const void *
  * pi_apply -- y = op x for op in {PI_OP_M, PI_OP_N, PI_OP_L} (the operators
  * of Eq. MatrixEquation), x and y device arrays of nx*ny*nz elements of the
  * plan's type; entries of x in masked cells are ignored, y is 0 there.
- * x and y must not overlap.  Asynchronous.
+ * x and y must not overlap and must be 16-byte aligned when the plan moves
+ * four cells per lane (pi_get_lane_cells == 4; torch allocations are), else
+ * PI_ERR_INVALID_ARG.  Asynchronous.
  */
 pi_status pi_apply(pi_plan_t plan, int op, const void *x, void *y, void *stream);
 
@@ -195,8 +202,9 @@ pi_status pi_time_kernel(pi_plan_t plan, int kernel, int32_t reps, double *avg_m
 
 /*
  * pi_autotune -- pick the tile (pi_set_tile) that minimises the time of one
- * outer step of Algorithm 1 for this plan: for each candidate segment length
- * it times the outer kernel once and the inner kernels `inner_iters` times
+ * outer step of Algorithm 1 for this plan: for each candidate (segment
+ * length, cells per lane) it times the outer kernel once and the inner
+ * kernels `inner_iters` times
  * (pi_time_kernel, `reps` launches each) and keeps the fastest.  Results are
  * cached per (ndim, dims, precision, inner solver) for the life of the process,
  * so later plans of the same shape take the cached tile without timing.  The

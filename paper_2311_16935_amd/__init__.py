@@ -76,10 +76,12 @@ def _load():
     lib.pi_source.restype = ctypes.c_int
     lib.pi_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     lib.pi_apply.restype = ctypes.c_int
-    lib.pi_set_tile.argtypes = [vp, ctypes.c_int32]
+    lib.pi_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     lib.pi_set_tile.restype = ctypes.c_int
     lib.pi_get_tile.argtypes = [vp]
     lib.pi_get_tile.restype = ctypes.c_int32
+    lib.pi_get_lane_cells.argtypes = [vp]
+    lib.pi_get_lane_cells.restype = ctypes.c_int32
     lib.pi_time_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(dbl), vp]
     lib.pi_time_kernel.restype = ctypes.c_int
     lib.pi_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp]
@@ -92,7 +94,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("pi_plan", "pi_plan_destroy", "pi_workspace_bytes", "pi_set_inner_iters", "pi_set_tile",
-            "pi_get_tile", "pi_solve",
+            "pi_get_tile", "pi_get_lane_cells", "pi_solve",
             "pi_solve_batched", "pi_source", "pi_apply", "pi_time_kernel", "pi_autotune", "pi_status_string")
 
 PI_K_OUTER, PI_K_SPMV, PI_K_UPDATE = 0, 1, 2
@@ -150,14 +152,18 @@ def pi_set_inner_iters(plan, iters: int) -> None:
         raise PiError(rc, "pi_set_inner_iters")
 
 
-def pi_set_tile(plan, mseg: int) -> None:
-    rc = lib.pi_set_tile(plan, int(mseg))
+def pi_set_tile(plan, mseg: int, lane_cells: int = 0) -> None:
+    rc = lib.pi_set_tile(plan, int(mseg), int(lane_cells))
     if rc != PI_OK:
         raise PiError(rc, "pi_set_tile")
 
 
 def pi_get_tile(plan) -> int:
     return int(lib.pi_get_tile(plan))
+
+
+def pi_get_lane_cells(plan) -> int:
+    return int(lib.pi_get_lane_cells(plan))
 
 
 def pi_solve(plan, gx, gy, gz, P, tol, max_iter, flags=0, stream=None):

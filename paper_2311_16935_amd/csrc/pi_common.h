@@ -1,16 +1,19 @@
 // Shared host/device definitions of libpi.
 //
-// Work decomposition.  A grid is cut into "strips": 64 consecutive cells
-// along x (one wavefront, one cell per lane) at fixed y (3-D), which march
-// along the slowest axis (z in 3-D, y in 2-D) over a segment of `mseg`
-// planes/rows.  The marching lane keeps the values of the previous and the
-// next plane in registers, so the stencil reads each vector from HBM about
-// once; x-neighbours come from adjacent lanes, y-neighbours in 3-D from L1/L2.
-// A block is four strips.  Every kernel of the solve walks a block table whose
-// entries name (instance, block-within-instance), so one launch serves one
-// grid or a whole batch of uneven grids; the table is ordered so that each
-// instance's consecutive blocks sit on one XCD (hardware assigns workgroup i
-// to XCD i mod 8), keeping plane-to-plane reuse inside one L2.
+// Work decomposition.  Stencil kernels cut a grid into "strips": 64 * W
+// consecutive cells along x (one wavefront, W cells per lane; W = 4 when nx
+// is a multiple of 4, else 1) at fixed y (3-D), which march along the
+// slowest axis (z in 3-D, y in 2-D) over a segment of `mseg` planes/rows.
+// The marching lane keeps the values of the previous and the next plane in
+// registers, so the stencil reads each vector from HBM about once;
+// x-neighbours come from the lane itself and adjacent lanes, y-neighbours in
+// 3-D from L1/L2.  A block is four strips.  Point-wise kernels instead give
+// block b of an instance a contiguous range of cells.  Every kernel of the
+// solve walks a block table whose entries name (instance,
+// block-within-instance), so one launch serves one grid or a whole batch of
+// uneven grids; the table is ordered so that each instance's consecutive
+// blocks sit on one XCD (hardware assigns workgroup i to XCD i mod 8), keeping
+// plane-to-plane reuse inside one L2.
 #pragma once
 
 #include <stdint.h>
@@ -24,10 +27,13 @@ constexpr int kXcd = 8;
 constexpr uint32_t kValidBit = 1u << 31;
 constexpr int kStates = 20;      // per-direction counter states (3-D uses 0..18)
 constexpr int kSegCells = 65536; // gauge segment length (cells)
-#ifndef PI_STREAM_DEPTH
-#define PI_STREAM_DEPTH 4
-#endif
-constexpr int kStream = PI_STREAM_DEPTH;  // cells per lane in flight, streaming kernels
+constexpr int kShapes = 8;       // stencil launch shapes: (2-D, 3-D) x (1, 4 cells per lane) x (codes read, derived)
+
+// Launch shape of an instance: bit 0 = 3-D, bit 1 = four cells per lane,
+// bit 2 = no mask (counter codes derived from cell coordinates).
+__host__ __device__ inline int shape_of(int ndim, int vw, int gen) {
+  return (ndim == 3 ? 1 : 0) | (vw == 4 ? 2 : 0) | (gen ? 4 : 0);
+}
 
 // Per-direction code layout: 3-D 5 bits (state = 1 + n1 + 3 n2 + 9 far for a
 // face neighbour with data, 0 otherwise), 2-D 3 bits (state = 1 + n1 + 3 far).
@@ -47,7 +53,9 @@ struct Inst {
   int32_t ndim;
   int32_t nx, ny, nz;
   int64_t ncell;
-  int32_t nxs;      // 64-wide strips along x
+  int32_t vw;       // cells per lane along x in stencil kernels (1 or 4)
+  int32_t gen;      // 1: every cell holds data, codes follow from coordinates
+  int32_t nxs;      // strips of 64 * vw cells along x
   int32_t rows;     // strips stacked along y: ny in 3-D, 1 in 2-D
   int32_t nm;       // length of the marching axis
   int32_t mseg;     // marching segment length
@@ -110,7 +118,8 @@ struct State {
   int32_t done;
   int32_t status;   // pi_status
   int32_t nonfinite;
-  uint32_t ticket;
+  int32_t tail;     // CG: the last inner iteration's alpha p is still to be
+                    // added to the correction (the outer kernel does it)
   int32_t pad;
 };
 

@@ -36,7 +36,7 @@ struct LaunchArgs {
   void *y;              // K_APPLY output
 };
 
-hipError_t launch(KernelId k, bool fp64, int ndim, const LaunchArgs &la);
+hipError_t launch(KernelId k, bool fp64, int shape, const LaunchArgs &la);
 
 // Kernels that leave per-block partial sums, and the per-instance finalize
 // (grid = count instances) that turns them into the instances' scalars.

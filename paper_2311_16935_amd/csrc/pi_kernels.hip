@@ -9,13 +9,17 @@
 // or atomic counter sits on the hot path, and results are bitwise
 // reproducible.
 //
-// Memory-level parallelism: a stencil wave fetches everything plane m+1
-// needs (operand, code word, source, y neighbours, strip-edge values) before
-// it computes plane m; streaming kernels load kStream cells per lane before
-// storing any of them.
+// Two ways of walking an instance's cells:
+//  * stencil kernels march: a wave owns a strip of 64 * W consecutive cells
+//    along x (W cells per lane, 16-byte loads when W = 4) and walks along the
+//    slowest axis, fetching everything plane m+1 needs (operand, code words,
+//    source, y neighbours, strip-edge values) while it computes plane m;
+//  * point-wise kernels stream a contiguous range of cells per block,
+//    16 bytes per lane per load, so each block reads long linear runs.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <string.h>
 
 #include "pi_common.h"
 #include "pi_kernels.h"
@@ -37,23 +41,76 @@ __device__ inline const PI_G T *gp(const void *p) {
 }
 
 // ---------------------------------------------------------------------------
-// work decomposition
+// short vectors: W consecutive cells of one array, moved with 16-byte
+// accesses (the caller guarantees 16-byte alignment when W * sizeof(T) >= 16)
+// ---------------------------------------------------------------------------
+template <typename V, int W>
+struct Vec {
+  V e[W];
+};
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int W, typename T>
+__device__ inline Vec<T, W> ldv(const PI_G T *p, int64_t c) {
+  Vec<T, W> v;
+  if constexpr (W * sizeof(T) < 16) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) v.e[k] = p[c + k];
+  } else {
+    const PI_G u32x4 *q = (const PI_G u32x4 *)(p + c);
+#pragma unroll
+    for (int i = 0; i < (int)(W * sizeof(T) / 16); ++i) {
+      const u32x4 u = q[i];
+      memcpy(&v.e[i * (16 / sizeof(T))], &u, 16);
+    }
+  }
+  return v;
+}
+
+template <int W, typename T>
+__device__ inline void stv(PI_G T *p, int64_t c, const Vec<T, W> &v) {
+  if constexpr (W * sizeof(T) < 16) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) p[c + k] = v.e[k];
+  } else {
+    PI_G u32x4 *q = (PI_G u32x4 *)(p + c);
+#pragma unroll
+    for (int i = 0; i < (int)(W * sizeof(T) / 16); ++i) {
+      u32x4 u;
+      memcpy(&u, &v.e[i * (16 / sizeof(T))], 16);
+      q[i] = u;
+    }
+  }
+}
+
+template <typename V, int W>
+__device__ inline Vec<V, W> vzero() {
+  Vec<V, W> z;
+#pragma unroll
+  for (int k = 0; k < W; ++k) z.e[k] = V(0);
+  return z;
+}
+
+// ---------------------------------------------------------------------------
+// stencil work decomposition
 // ---------------------------------------------------------------------------
 // Everything a wave needs while it walks its segment, copied out of the
 // instance record once: the compiler cannot keep fields of a global struct
 // in registers across the kernel's own stores.
 struct Walk {
-  int64_t base;   // storage index of this lane's column at march position 0
+  int64_t base;   // storage index of this lane's first cell at march position 0
   int64_t sm;     // stride of the march axis
   const PI_G uint32_t *code;
   int m0, m1;     // march range of this wave (uniform over the wave)
   int nm;         // length of the march axis
-  int nx, ny;
-  int x;          // x of this lane
+  int nx, ny, nz;
+  int x;          // x of this lane's first cell
   int row;        // y of this wave's strip (3-D)
-  bool act;       // lane owns a cell column inside the grid
+  bool act;       // lane owns cells inside the grid
 };
 
+template <int W>
 __device__ inline Walk make_walk(const Inst &in, int lb) {
   Walk k;
   k.sm = in.sm;
@@ -61,6 +118,7 @@ __device__ inline Walk make_walk(const Inst &in, int lb) {
   k.nm = in.nm;
   k.nx = in.nx;
   k.ny = in.ny;
+  k.nz = in.nz;
   k.m0 = k.m1 = 0;
   k.x = k.row = 0;
   k.base = 0;
@@ -84,14 +142,15 @@ __device__ inline Walk make_walk(const Inst &in, int lb) {
     seg = w / in.nxs;
     row = 0;
   }
-  k.x = (int)(xs * kWave + lane);
+  k.x = (int)(xs * kWave * W + lane * W);
   k.m0 = (int)(seg * in.mseg);
   k.m1 = min(k.m0 + in.mseg, in.nm);
   k.act = k.x < in.nx;
   k.row = (int)row;
-  // lanes past the end of a partial strip address the strip's last cell, so
-  // that every load is in bounds without a branch; they never store
-  k.base = (int64_t)min(k.x, in.nx - 1) + row * in.srow;
+  // lanes past the end of a partial strip address the strip's last cells
+  // (nx is a multiple of W), so that every load is in bounds without a
+  // branch; they never store
+  k.base = (int64_t)min(k.x, in.nx - W) + row * in.srow;
   return k;
 }
 
@@ -99,87 +158,170 @@ __device__ inline int dstate(uint32_t code, int d, int bits) {
   return (int)((code >> (bits * d)) & ((1u << bits) - 1u));
 }
 
-// One plane of a marching wave: everything the stencil needs at a cell,
-// fetched one plane ahead of its use.  vN/vS are the y neighbours (3-D only),
-// vEdge the x neighbour beyond the strip end (lane 0: west, lane 63: east).
+// Counter code of a cell of a grid without missing data, from its
+// coordinates: the same word the plan stores (face neighbour J = C + s e_a
+// inside the grid; laterals of J with data along each remaining axis; far
+// cell J + s e_a inside the grid), since every in-grid cell holds data.
+template <int ND>
+__device__ inline uint32_t code_at(int x, int y, int z, int nx, int ny, int nz) {
+  const int c[3] = {x, y, z}, n[3] = {nx, ny, nz};
+  int side[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) side[k] = (c[k] >= 1) + (c[k] + 1 < n[k]);
+  const int bits = dir_bits(ND);
+  uint32_t out = kValidBit;
+#pragma unroll
+  for (int d = 0; d < 2 * ND; ++d) {
+    const int a = d >> 1, s = (d & 1) ? -1 : 1;
+    const int j = c[a] + s, f = c[a] + 2 * s;
+    if (j < 0 || j >= n[a]) continue;
+    const int far = f >= 0 && f < n[a];
+    const int l0 = a == 0 ? 1 : 0, l1 = a == 2 ? 1 : 2;
+    const uint32_t state = ND == 3 ? 1u + side[l0] + 3u * side[l1] + 9u * far : 1u + side[l0] + 3u * far;
+    out |= state << (bits * d);
+  }
+  return out;
+}
+
+// What the stencil body sees at one cell: its operand value, the y
+// neighbours (3-D only), the extra per-cell input and the code word.
 // Neighbours outside the grid read as 0; internal vectors hold 0 in masked
 // cells, and every neighbour value is used only through its counter state.
 template <typename V, typename A>
-struct Plane {
-  V v, vN, vS, vEdge;
+struct Cell {
+  V v, vN, vS;
   A aux;
   uint32_t code;
 };
 
+// One plane of a lane's W cells, fetched one plane ahead of its use.  vEdge
+// is the x neighbour beyond the strip end (lane 0: west, lane 63: east).
+template <typename V, typename A, int W>
+struct Plane {
+  Vec<V, W> v, vN, vS;
+  Vec<A, W> aux;
+  Vec<uint32_t, W> code;
+  V vEdge;
+};
+
 // March one wave along its segment.
-//   load(c)   stencil operand at an in-grid cell c
-//   aux(c)    extra per-cell input (the source in the outer step)
-//   body(c, plane, vW, vE, vPrev, vNext) -> Out   one cell; x neighbours come
-//             from adjacent lanes, march-axis neighbours from registers
-//   store(c, out)
-template <int ND, typename V, typename A, typename Out, typename Load, typename Aux, typename Body,
-          typename Store>
-__device__ inline void march(const Walk &wk, Load load, Aux aux, Body body, Store store) {
+//   load(c)   -> Vec<V, W>  stencil operand at cells c .. c+W-1
+//   load1(c)  -> V          stencil operand at one cell (strip edges)
+//   aux(c)    -> Vec<A, W>  extra per-cell input
+//   body(c, cell, vW, vE, vPrev, vNext) -> Out   one cell; x neighbours come
+//             from the lane's own cells and adjacent lanes, march-axis
+//             neighbours from registers
+//   store(c, const Out (&)[W])
+template <int ND, int W, bool GEN, typename V, typename A, typename Out, typename Load, typename Load1, typename Aux,
+          typename Body, typename Store>
+__device__ inline void march(const Walk &wk, Load load, Load1 load1, Aux aux, Body body, Store store) {
   if (wk.m1 <= wk.m0) return;  // uniform over the wave
   const int lane = threadIdx.x & 63;
   const bool hasN = ND == 3 && wk.row + 1 < wk.ny, hasS = ND == 3 && wk.row > 0;
-  const bool edgeW = lane == 0 && wk.x > 0, edgeE = lane == kWave - 1 && wk.x + 1 < wk.nx;
+  const bool edgeW = lane == 0 && wk.x > 0, edgeE = lane == kWave - 1 && wk.x + W < wk.nx;
   const int64_t snx = wk.nx;
   // neighbour offsets resolved once; a neighbour that does not exist reads
   // the cell itself and is zeroed, so no load sits behind a branch
   const int64_t offN = hasN ? snx : 0, offS = hasS ? -snx : 0;
-  const int64_t offE = edgeW ? -1 : edgeE ? 1 : 0;
+  const int64_t offE = edgeW ? -1 : edgeE ? W : 0;
   const bool hasEdge = edgeW || edgeE;
   const PI_G uint32_t *code = wk.code;
-  auto fetch = [&](int64_t c, Plane<V, A> &pl) {
+  // codes of an unmasked grid follow from (x, y, z): 3-D (x, row, m), 2-D (x, m, 0)
+  auto codes = [&](int64_t c, int m) {
+    if constexpr (GEN) {
+      Vec<uint32_t, W> v;
+#pragma unroll
+      for (int k = 0; k < W; ++k)
+        v.e[k] = ND == 3 ? code_at<3>(wk.x + k, wk.row, m, wk.nx, wk.ny, wk.nz)
+                         : code_at<2>(wk.x + k, m, 0, wk.nx, wk.ny, 1);
+      return v;
+    } else {
+      return ldv<W>(code, c);
+    }
+  };
+  auto fetch = [&](int64_t c, int m, Plane<V, A, W> &pl) {
     pl.v = load(c);
-    pl.code = code[c];
+    pl.code = codes(c, m);
     pl.aux = aux(c);
     if (ND == 3) {
-      const V n = load(c + offN), s = load(c + offS);
-      pl.vN = hasN ? n : V(0);
-      pl.vS = hasS ? s : V(0);
+      const Vec<V, W> n = load(c + offN), s = load(c + offS);
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        pl.vN.e[k] = hasN ? n.e[k] : V(0);
+        pl.vS.e[k] = hasS ? s.e[k] : V(0);
+      }
     }
-    const V e = load(c + offE);
+    const V e = load1(c + offE);
     pl.vEdge = hasEdge ? e : V(0);
   };
   const int64_t sm = wk.sm;
   int64_t c = wk.base + (int64_t)wk.m0 * sm;
-  V prev = wk.m0 > 0 ? load(c - sm) : V(0);
-  Plane<V, A> cur, nxt;
-  fetch(c, cur);
+  Vec<V, W> prev = wk.m0 > 0 ? load(c - sm) : vzero<V, W>();
+  Plane<V, A, W> cur, nxt;
+  fetch(c, wk.m0, cur);
   for (int m = wk.m0; m < wk.m1; ++m, c += sm) {
     // uniform over the wave: the whole next plane, or only its values when
     // it is the next segment's first plane, or nothing past the grid
     if (m + 1 < wk.m1)
-      fetch(c + sm, nxt);
+      fetch(c + sm, m + 1, nxt);
     else
-      nxt.v = m + 1 < wk.nm ? load(c + sm) : V(0);
-    V vW = __shfl_up(cur.v, 1, kWave);
-    V vE = __shfl_down(cur.v, 1, kWave);
-    if (lane == 0) vW = cur.vEdge;
-    if (lane == kWave - 1) vE = cur.vEdge;
-    if (wk.act) store(c, body(c, cur, vW, vE, prev, nxt.v));
+      nxt.v = m + 1 < wk.nm ? load(c + sm) : vzero<V, W>();
+    V left = __shfl_up(cur.v.e[W - 1], 1, kWave);
+    V right = __shfl_down(cur.v.e[0], 1, kWave);
+    if (lane == 0) left = cur.vEdge;
+    if (lane == kWave - 1) right = cur.vEdge;
+    // lanes past the grid only serve the shuffles: they neither compute
+    // (their cells duplicate a neighbour's, which would enter the sums) nor store
+    if (wk.act) {
+      Out o[W];
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        const V vW = k == 0 ? left : cur.v.e[k > 0 ? k - 1 : 0];
+        const V vE = k == W - 1 ? right : cur.v.e[k + 1 < W ? k + 1 : 0];
+        Cell<V, A> cl;
+        cl.v = cur.v.e[k];
+        cl.vN = ND == 3 ? cur.vN.e[k] : V(0);
+        cl.vS = ND == 3 ? cur.vS.e[k] : V(0);
+        cl.aux = cur.aux.e[k];
+        cl.code = cur.code.e[k];
+        o[k] = body(c + k, cl, vW, vE, prev.e[k], nxt.v.e[k]);
+      }
+      store(c, o);
+    }
     prev = cur.v;
     cur = nxt;
   }
 }
 
-// Stream over the cells of one wave's segment, kStream cells per lane at a
-// time: f.load(c, u) for all u first, then f.apply(c, u).
-template <typename F>
-__device__ inline void stream(const Walk &wk, F &f) {
-  if (!wk.act) return;
-  const int64_t sm = wk.sm;
-  for (int m = wk.m0; m < wk.m1; m += kStream) {
-    const int64_t cm = wk.base + (int64_t)m * sm;
+// ---------------------------------------------------------------------------
+// point-wise work decomposition: block lb of an instance owns the cells
+// [lb * per, (lb + 1) * per) with per a multiple of 1024
+// ---------------------------------------------------------------------------
+__device__ inline void linear_range(const Inst &in, int lb, int64_t &beg, int64_t &end) {
+  const int64_t g = 1024;
+  const int64_t per = ((in.ncell + in.nblocks - 1) / in.nblocks + g - 1) / g * g;
+  beg = min(in.ncell, (int64_t)lb * per);
+  end = min(in.ncell, beg + per);
+}
+
+// Stream [beg, end) with E cells per lane per access and U accesses in
+// flight: f.load(c, u) / f.apply(c, u) for E cells at c, f.one(c) for a
+// single cell at the ragged end of the array.
+template <int E, int U, typename F>
+__device__ inline void stream_linear(int64_t beg, int64_t end, F &f) {
+  const int64_t step = (int64_t)kBlock * E;
+  int64_t c = beg + (int64_t)threadIdx.x * E;
+  for (; c + (U - 1) * step + E <= end; c += U * step) {
 #pragma unroll
-    for (int u = 0; u < kStream; ++u)
-      if (m + u < wk.m1) f.load(cm + (int64_t)u * sm, u);
+    for (int u = 0; u < U; ++u) f.load(c + u * step, u);
 #pragma unroll
-    for (int u = 0; u < kStream; ++u)
-      if (m + u < wk.m1) f.apply(cm + (int64_t)u * sm, u);
+    for (int u = 0; u < U; ++u) f.apply(c + u * step, u);
   }
+  for (; c + E <= end; c += step) {
+    f.load(c, 0);
+    f.apply(c, 0);
+  }
+  for (; c < end; ++c) f.one(c);  // at most E - 1 cells, last block only
 }
 
 // ---------------------------------------------------------------------------
@@ -242,31 +384,30 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_init(const BlockEnt *tab, const Inst *insts, State *sts, double *part,
                                                  int warm) {
   PI_PROLOGUE
-  const Walk wk = make_walk(in, e.lb);
+  int64_t beg, end;
+  linear_range(in, e.lb, beg, end);
   const T *P0 = (const T *)in.P0;
   double *P = in.P[0];
   T *d = (T *)in.d;
   T *p0 = (T *)in.p[0], *p1 = (T *)in.p[1], *v = (T *)in.bs[1];
+  const uint32_t *code = in.code;
   int bad = 0;
-  if (wk.act) {
-    int64_t c = wk.base + (int64_t)wk.m0 * wk.sm;
-    for (int m = wk.m0; m < wk.m1; ++m, c += wk.sm) {
-      // no correction before the first outer step, and finite search
-      // directions for the first inner iteration (which scales them by 0)
-      d[c] = T(0);
-      p0[c] = T(0);
-      p1[c] = T(0);
-      if (v) v[c] = T(0);
-      double v = 0.0;
-      if (warm && (wk.code[c] & kValidBit)) {
-        v = (double)P0[c];
-        if (!isfinite(v)) {
-          bad = 1;
-          v = 0.0;
-        }
+  for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
+    // no correction before the first outer step, and finite search
+    // directions for the first inner iteration (which scales them by 0)
+    d[c] = T(0);
+    p0[c] = T(0);
+    p1[c] = T(0);
+    if (v) v[c] = T(0);
+    double x = 0.0;
+    if (warm && (code[c] & kValidBit)) {
+      x = (double)P0[c];
+      if (!isfinite(x)) {
+        bad = 1;
+        x = 0.0;
       }
-      P[c] = v;
     }
+    P[c] = x;
   }
   if (bad) atomicOr(&st->nonfinite, 1);
 }
@@ -281,10 +422,12 @@ __global__ __launch_bounds__(kBlock) void k_init(const BlockEnt *tab, const Inst
 template <typename T, int ND>
 __global__ __launch_bounds__(kBlock) void k_source(const BlockEnt *tab, const Inst *insts, State *sts, double *part) {
   PI_PROLOGUE
-  const Walk wk = make_walk(in, e.lb);
+  int64_t beg, end;
+  linear_range(in, e.lb, beg, end);
   const T *g[3] = {(const T *)in.g[0], (const T *)in.g[1], (const T *)in.g[2]};
   T *S = (T *)in.S;
   double *S64 = in.S64;
+  const uint32_t *code = in.code;
   const int bits = dir_bits(ND);
   const int64_t off[6] = {1, -1, (int64_t)in.nx, -(int64_t)in.nx, ND == 3 ? (int64_t)in.nx * in.ny : 0,
                           ND == 3 ? -(int64_t)in.nx * in.ny : 0};
@@ -293,31 +436,28 @@ __global__ __launch_bounds__(kBlock) void k_source(const BlockEnt *tab, const In
   for (int d = 0; d < 6; ++d) w[d] = -0.5 * in.dsig[d] * in.a[d];
   double acc[1] = {0.0};
   int bad = 0;
-  if (wk.act) {
-    int64_t c = wk.base + (int64_t)wk.m0 * wk.sm;
-    for (int m = wk.m0; m < wk.m1; ++m, c += wk.sm) {
-      const uint32_t cd = wk.code[c];
-      double s = 0.0;
-      if (cd & kValidBit) {
-        double own[3];
+  for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
+    const uint32_t cd = code[c];
+    double s = 0.0;
+    if (cd & kValidBit) {
+      double own[3];
 #pragma unroll
-        for (int a = 0; a < ND; ++a) {
-          own[a] = (double)g[a][c];
-          if (!isfinite(own[a])) bad = 1;
-        }
+      for (int a = 0; a < ND; ++a) {
+        own[a] = (double)g[a][c];
+        if (!isfinite(own[a])) bad = 1;
+      }
 #pragma unroll
-        for (int d = 0; d < 2 * ND; ++d) {
-          if (dstate(cd, d, bits)) {
-            const int a = d >> 1;
-            const double nb = (double)g[a][c + off[d]];
-            s += w[d] * (nb + own[a]);
-          }
+      for (int d = 0; d < 2 * ND; ++d) {
+        if (dstate(cd, d, bits)) {
+          const int a = d >> 1;
+          const double nb = (double)g[a][c + off[d]];
+          s += w[d] * (nb + own[a]);
         }
       }
-      S64[c] = s;
-      if (S) S[c] = (T)s;
-      acc[0] += s * s;
     }
+    S64[c] = s;
+    if (S) S[c] = (T)s;
+    acc[0] += s * s;
   }
   if (bad) atomicOr(&st->nonfinite, 1);
   publish<1>(in, part, e.lb, acc);
@@ -329,16 +469,21 @@ __global__ __launch_bounds__(kBlock) void k_source(const BlockEnt *tab, const In
 // (M - N) is applied as sum_j a_j (P_C - P_J) over face neighbours holding
 // data: its off-diagonal entries are -(w_j^{n+1} + w_j^n) = -a_j and, since
 // all counters of a data cell add up to A_tot, its diagonal 1 - w_C^n equals
-// sum_j a_j.
-template <typename T, int ND>
+// sum_j a_j.  With CG the last inner iteration's update is folded in here:
+// delta = d + alpha p (the residual it would also update is recomputed from
+// scratch anyway), which saves one pass over four vectors per outer step.
+template <typename T, int ND, int W, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Inst *insts, State *sts, double *part) {
   PI_PROLOGUE
   if (skip_outer(st)) return;
-  const Walk wk = make_walk(in, e.lb);
+  const Walk wk = make_walk<W>(in, e.lb);
   const int cur = st->Pcur;
-  const bool hd = st->have_delta != 0;
   const PI_G double *Pold = gp<double>(in.P[cur]);
   PI_G double *Pnew = gp<double>(in.P[cur ^ 1]);
+  // p is zero before the first inner solve and finite after it, so the
+  // fold needs no branch: at = 0 when nothing is pending
+  const T at = st->tail ? (T)st->alpha : T(0);
+  const PI_G T *pt = gp<T>(in.p[st->pcur]);
   const PI_G T *dl = gp<T>(in.d);
   const PI_G double *S = gp<double>(in.S64);
   PI_G T *res = gp<T>(in.res);
@@ -350,14 +495,35 @@ __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Ins
   struct Out {
     double p, r;
   };
-  // delta is zero before the first outer step (set when the solve starts)
-  auto load = [&](int64_t c) -> double { return Pold[c] + (double)dl[c]; };
   struct Aux {
     double S, d;
   };
-  auto aux = [&](int64_t c) -> Aux { return Aux{S[c], (double)dl[c]}; };
-  auto body = [&](int64_t c, const Plane<double, Aux> &pl, double vW, double vE, double vP,
-                  double vN) -> Out {
+  // delta is zero before the first outer step (set when the solve starts)
+  auto delta = [&](int64_t c) {
+    const Vec<T, W> d = ldv<W>(dl, c), p = ldv<W>(pt, c);
+    Vec<T, W> v;
+#pragma unroll
+    for (int k = 0; k < W; ++k) v.e[k] = d.e[k] + at * p.e[k];
+    return v;
+  };
+  auto load = [&](int64_t c) {
+    const Vec<double, W> P = ldv<W>(Pold, c);
+    const Vec<T, W> d = delta(c);
+    Vec<double, W> v;
+#pragma unroll
+    for (int k = 0; k < W; ++k) v.e[k] = P.e[k] + (double)d.e[k];
+    return v;
+  };
+  auto load1 = [&](int64_t c) -> double { return Pold[c] + (double)(dl[c] + at * pt[c]); };
+  auto aux = [&](int64_t c) {
+    const Vec<double, W> s = ldv<W>(S, c);
+    const Vec<T, W> d = delta(c);
+    Vec<Aux, W> x;
+#pragma unroll
+    for (int k = 0; k < W; ++k) x.e[k] = Aux{s.e[k], (double)d.e[k]};
+    return x;
+  };
+  auto body = [&](int64_t, const Cell<double, Aux> &pl, double vW, double vE, double vP, double vN) -> Out {
     const uint32_t cd = pl.code;
     if (!(cd & kValidBit)) return Out{0.0, 0.0};
     const double vC = pl.v;
@@ -381,26 +547,54 @@ __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Ins
     acc[3] += vC * vC;
     return Out{vC, r};
   };
-  auto store = [&](int64_t c, const Out &o) {
-    Pnew[c] = o.p;
-    res[c] = (T)o.r;
+  auto store = [&](int64_t c, const Out (&o)[W]) {
+    Vec<double, W> p;
+    Vec<T, W> r;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      p.e[k] = o[k].p;
+      r.e[k] = (T)o[k].r;
+    }
+    stv<W>(Pnew, c, p);
+    stv<W>(res, c, r);
   };
-  march<ND, double, Aux, Out>(wk, load, aux, body, store);
+  march<ND, W, GEN, double, Aux, Out>(wk, load, load1, aux, body, store);
   publish<4>(in, part, e.lb, acc);
 }
 
 // ---------------------------------------------------------------------------
 // inner conjugate gradient on M delta = r
 // ---------------------------------------------------------------------------
-// p <- r + beta p (or p <- r on the first iteration), q <- M p, p.q
+// The inner operator [W^{n+1}]: s = v_C - sum_j w_j^{n+1} v_J over face
+// neighbours J holding data, weights from the per-state LUT.
 template <typename T, int ND>
+__device__ inline T apply_m(const T (*lut)[kStates], uint32_t cd, int bits, T vC, T vW, T vE, T vN, T vS, T vP,
+                            T vNx) {
+  T s = vC;
+  int t;
+  if ((t = dstate(cd, DE, bits))) s -= lut[DE][t] * vE;
+  if ((t = dstate(cd, DW, bits))) s -= lut[DW][t] * vW;
+  if (ND == 3) {
+    if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * vN;
+    if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * vS;
+    if ((t = dstate(cd, DF, bits))) s -= lut[DF][t] * vNx;
+    if ((t = dstate(cd, DB, bits))) s -= lut[DB][t] * vP;
+  } else {
+    if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * vNx;
+    if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * vP;
+  }
+  return s;
+}
+
+// p <- r + beta p (or p <- r on the first iteration), q <- M p, p.q
+template <typename T, int ND, int W, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv(const BlockEnt *tab, const Inst *insts, State *sts,
                                                     double *part) {
   PI_PROLOGUE
   if (skip_inner(in, st)) return;
   __shared__ T lut[6][kStates];
   load_lut<T>(in.lut_np1, lut);
-  const Walk wk = make_walk(in, e.lb);
+  const Walk wk = make_walk<W>(in, e.lb);
   // beta is 0 on the first iteration and the old direction is finite, so
   // the direction update needs no branch
   const T beta = (T)st->beta;
@@ -414,32 +608,34 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const BlockEnt *tab, const I
   struct Out {
     T p, q;
   };
-  auto load = [&](int64_t c) -> T { return res[c] + beta * pold[c]; };
-  auto body = [&](int64_t c, const Plane<T, int> &pl, T vW, T vE, T vP, T vN) -> Out {
+  auto load = [&](int64_t c) {
+    const Vec<T, W> r = ldv<W>(res, c), p = ldv<W>(pold, c);
+    Vec<T, W> v;
+#pragma unroll
+    for (int k = 0; k < W; ++k) v.e[k] = r.e[k] + beta * p.e[k];
+    return v;
+  };
+  auto load1 = [&](int64_t c) -> T { return res[c] + beta * pold[c]; };
+  auto aux = [](int64_t) { return Vec<int, W>{}; };
+  auto body = [&](int64_t, const Cell<T, int> &pl, T vW, T vE, T vP, T vN) -> Out {
     const uint32_t cd = pl.code;
     const T vC = pl.v;
     if (!(cd & kValidBit)) return Out{T(0), T(0)};
-    T s = vC;
-    int t;
-    if ((t = dstate(cd, DE, bits))) s -= lut[DE][t] * vE;
-    if ((t = dstate(cd, DW, bits))) s -= lut[DW][t] * vW;
-    if (ND == 3) {
-      if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * pl.vN;
-      if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * pl.vS;
-      if ((t = dstate(cd, DF, bits))) s -= lut[DF][t] * vN;
-      if ((t = dstate(cd, DB, bits))) s -= lut[DB][t] * vP;
-    } else {
-      if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * vN;
-      if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * vP;
-    }
+    const T s = apply_m<T, ND>(lut, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN);
     acc[0] += (double)vC * (double)s;
     return Out{vC, s};
   };
-  auto store = [&](int64_t c, const Out &o) {
-    pnew[c] = o.p;
-    q[c] = o.q;
+  auto store = [&](int64_t c, const Out (&o)[W]) {
+    Vec<T, W> pv, qv;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      pv.e[k] = o[k].p;
+      qv.e[k] = o[k].q;
+    }
+    stv<W>(pnew, c, pv);
+    stv<W>(q, c, qv);
   };
-  march<ND, T, int, Out>(wk, load, [](int64_t) { return 0; }, body, store);
+  march<ND, W, GEN, T, int, Out>(wk, load, load1, aux, body, store);
   publish<1>(in, part, e.lb, acc);
 }
 
@@ -447,21 +643,34 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const BlockEnt *tab, const I
 // r <- r - alpha q, r.r
 template <typename T>
 struct CgUpdate {
+  static constexpr int E = 16 / sizeof(T);
+  static constexpr int U = 2;
   const PI_G T *p, *q;
   PI_G T *res, *d;
   T alpha;
   bool first;
   double acc;
-  T pv[kStream], qv[kStream], rv[kStream], dv[kStream];
+  Vec<T, E> pv[U], qv[U], rv[U], dv[U];
   __device__ void load(int64_t c, int u) {
-    pv[u] = p[c];
-    qv[u] = q[c];
-    rv[u] = res[c];
-    dv[u] = first ? T(0) : d[c];
+    pv[u] = ldv<E>(p, c);
+    qv[u] = ldv<E>(q, c);
+    rv[u] = ldv<E>(res, c);
+    dv[u] = first ? vzero<T, E>() : ldv<E>(d, c);
   }
   __device__ void apply(int64_t c, int u) {
-    const T r = rv[u] - alpha * qv[u];
-    d[c] = dv[u] + alpha * pv[u];
+    Vec<T, E> r, dn;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      r.e[k] = rv[u].e[k] - alpha * qv[u].e[k];
+      dn.e[k] = dv[u].e[k] + alpha * pv[u].e[k];
+      acc += (double)r.e[k] * (double)r.e[k];
+    }
+    stv<E>(d, c, dn);
+    stv<E>(res, c, r);
+  }
+  __device__ void one(int64_t c) {
+    const T r = res[c] - alpha * q[c];
+    d[c] = (first ? T(0) : d[c]) + alpha * p[c];
     res[c] = r;
     acc += (double)r * (double)r;
   }
@@ -472,7 +681,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const BlockEnt *tab, const
                                                       double *part) {
   PI_PROLOGUE
   if (skip_inner(in, st)) return;
-  const Walk wk = make_walk(in, e.lb);
+  int64_t beg, end;
+  linear_range(in, e.lb, beg, end);
   CgUpdate<T> f;
   f.p = gp<T>(in.p[st->pcur]);
   f.q = gp<T>(in.q);
@@ -481,7 +691,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const BlockEnt *tab, const
   f.alpha = (T)st->alpha;
   f.first = st->inner == 0;
   f.acc = 0.0;
-  stream(wk, f);
+  stream_linear<CgUpdate<T>::E, CgUpdate<T>::U>(beg, end, f);
   double acc[1] = {f.acc};
   publish<1>(in, part, e.lb, acc);
 }
@@ -490,14 +700,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const BlockEnt *tab, const
 // inner BiCGStab on M delta = r (shadow residual = the outer residual)
 // ---------------------------------------------------------------------------
 // phase 1: p <- r + beta (p - omega v) (p <- r first), v' <- M p (into q), rhat.v'
-template <typename T, int ND>
+template <typename T, int ND, int W, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_bicg_spmv_p(const BlockEnt *tab, const Inst *insts, State *sts,
                                                         double *part) {
   PI_PROLOGUE
   if (skip_inner(in, st)) return;
   __shared__ T lut[6][kStates];
   load_lut<T>(in.lut_np1, lut);
-  const Walk wk = make_walk(in, e.lb);
+  const Walk wk = make_walk<W>(in, e.lb);
   const T beta = (T)st->beta, omega = (T)st->omega;
   const int pc = st->pcur;
   const PI_G T *pold = gp<T>(in.p[pc]);
@@ -511,44 +721,46 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_p(const BlockEnt *tab, con
   struct Out {
     T p, v;
   };
-  auto load = [&](int64_t c) -> T { return res[c] + beta * (pold[c] - omega * v[c]); };
-  auto body = [&](int64_t c, const Plane<T, int> &pl, T vW, T vE, T vP, T vN) -> Out {
+  auto load = [&](int64_t c) {
+    const Vec<T, W> r = ldv<W>(res, c), p = ldv<W>(pold, c), vv = ldv<W>(v, c);
+    Vec<T, W> o;
+#pragma unroll
+    for (int k = 0; k < W; ++k) o.e[k] = r.e[k] + beta * (p.e[k] - omega * vv.e[k]);
+    return o;
+  };
+  auto load1 = [&](int64_t c) -> T { return res[c] + beta * (pold[c] - omega * v[c]); };
+  auto aux = [&](int64_t c) { return ldv<W>(rhat, c); };
+  auto body = [&](int64_t, const Cell<T, T> &pl, T vW, T vE, T vP, T vN) -> Out {
     const uint32_t cd = pl.code;
     const T vC = pl.v;
     if (!(cd & kValidBit)) return Out{T(0), T(0)};
-    T s = vC;
-    int t;
-    if ((t = dstate(cd, DE, bits))) s -= lut[DE][t] * vE;
-    if ((t = dstate(cd, DW, bits))) s -= lut[DW][t] * vW;
-    if (ND == 3) {
-      if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * pl.vN;
-      if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * pl.vS;
-      if ((t = dstate(cd, DF, bits))) s -= lut[DF][t] * vN;
-      if ((t = dstate(cd, DB, bits))) s -= lut[DB][t] * vP;
-    } else {
-      if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * vN;
-      if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * vP;
-    }
-    acc[0] += (double)rhat[c] * (double)s;
+    const T s = apply_m<T, ND>(lut, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN);
+    acc[0] += (double)pl.aux * (double)s;
     return Out{vC, s};
   };
-  auto store = [&](int64_t c, const Out &o) {
-    pnew[c] = o.p;
-    vnew[c] = o.v;
+  auto store = [&](int64_t c, const Out (&o)[W]) {
+    Vec<T, W> pv, vv;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      pv.e[k] = o[k].p;
+      vv.e[k] = o[k].v;
+    }
+    stv<W>(pnew, c, pv);
+    stv<W>(vnew, c, vv);
   };
-  march<ND, T, int, Out>(wk, load, [](int64_t) { return 0; }, body, store);
+  march<ND, W, GEN, T, T, Out>(wk, load, load1, aux, body, store);
   publish<1>(in, part, e.lb, acc);
 }
 
 // phase 2: v <- v', s <- r - alpha v, t <- M s, t.s and t.t
-template <typename T, int ND>
+template <typename T, int ND, int W, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_bicg_spmv_s(const BlockEnt *tab, const Inst *insts, State *sts,
                                                         double *part) {
   PI_PROLOGUE
   if (skip_inner(in, st)) return;
   __shared__ T lut[6][kStates];
   load_lut<T>(in.lut_np1, lut);
-  const Walk wk = make_walk(in, e.lb);
+  const Walk wk = make_walk<W>(in, e.lb);
   const T alpha = (T)st->alpha;
   const PI_G T *res = gp<T>(in.res);
   const PI_G T *vnew = gp<T>(in.q);
@@ -560,59 +772,75 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_s(const BlockEnt *tab, con
   struct Out {
     T v, s, t;
   };
-  auto load = [&](int64_t c) -> T { return res[c] - alpha * vnew[c]; };
-  auto body = [&](int64_t c, const Plane<T, int> &pl, T vW, T vE, T vP, T vN) -> Out {
+  auto load = [&](int64_t c) {
+    const Vec<T, W> r = ldv<W>(res, c), vv = ldv<W>(vnew, c);
+    Vec<T, W> o;
+#pragma unroll
+    for (int k = 0; k < W; ++k) o.e[k] = r.e[k] - alpha * vv.e[k];
+    return o;
+  };
+  auto load1 = [&](int64_t c) -> T { return res[c] - alpha * vnew[c]; };
+  auto aux = [&](int64_t c) { return ldv<W>(vnew, c); };
+  auto body = [&](int64_t, const Cell<T, T> &pl, T vW, T vE, T vP, T vN) -> Out {
     const uint32_t cd = pl.code;
     const T vC = pl.v;
-    const T vv = vnew[c];
+    const T vv = pl.aux;
     if (!(cd & kValidBit)) return Out{vv, T(0), T(0)};
-    T s = vC;
-    int t;
-    if ((t = dstate(cd, DE, bits))) s -= lut[DE][t] * vE;
-    if ((t = dstate(cd, DW, bits))) s -= lut[DW][t] * vW;
-    if (ND == 3) {
-      if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * pl.vN;
-      if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * pl.vS;
-      if ((t = dstate(cd, DF, bits))) s -= lut[DF][t] * vN;
-      if ((t = dstate(cd, DB, bits))) s -= lut[DB][t] * vP;
-    } else {
-      if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * vN;
-      if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * vP;
-    }
+    const T s = apply_m<T, ND>(lut, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN);
     acc[0] += (double)s * (double)vC;
     acc[1] += (double)s * (double)s;
     return Out{vv, vC, s};
   };
-  auto store = [&](int64_t c, const Out &o) {
-    v[c] = o.v;
-    s_out[c] = o.s;
-    t_out[c] = o.t;
+  auto store = [&](int64_t c, const Out (&o)[W]) {
+    Vec<T, W> a, b, d;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      a.e[k] = o[k].v;
+      b.e[k] = o[k].s;
+      d.e[k] = o[k].t;
+    }
+    stv<W>(v, c, a);
+    stv<W>(s_out, c, b);
+    stv<W>(t_out, c, d);
   };
-  march<ND, T, int, Out>(wk, load, [](int64_t) { return 0; }, body, store);
+  march<ND, W, GEN, T, T, Out>(wk, load, load1, aux, body, store);
   publish<2>(in, part, e.lb, acc);
 }
 
 // phase 3: delta <- delta + alpha p + omega s, r <- s - omega t, rhat.r
 template <typename T>
 struct BicgUpdate {
+  static constexpr int E = 16 / sizeof(T);
+  static constexpr int U = 1;
   const PI_G T *p, *s, *t, *rhat;
   PI_G T *res, *d;
   T alpha, omega;
   bool first;
   double acc;
-  T pv[kStream], sv[kStream], tv[kStream], hv[kStream], dv[kStream];
+  Vec<T, E> pv[U], sv[U], tv[U], hv[U], dv[U];
   __device__ void load(int64_t c, int u) {
-    pv[u] = p[c];
-    sv[u] = s[c];
-    tv[u] = t[c];
-    hv[u] = rhat[c];
-    dv[u] = first ? T(0) : d[c];
+    pv[u] = ldv<E>(p, c);
+    sv[u] = ldv<E>(s, c);
+    tv[u] = ldv<E>(t, c);
+    hv[u] = ldv<E>(rhat, c);
+    dv[u] = first ? vzero<T, E>() : ldv<E>(d, c);
   }
   __device__ void apply(int64_t c, int u) {
-    d[c] = dv[u] + (alpha * pv[u] + omega * sv[u]);
-    const T r = sv[u] - omega * tv[u];
+    Vec<T, E> dn, r;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      dn.e[k] = dv[u].e[k] + (alpha * pv[u].e[k] + omega * sv[u].e[k]);
+      r.e[k] = sv[u].e[k] - omega * tv[u].e[k];
+      acc += (double)hv[u].e[k] * (double)r.e[k];
+    }
+    stv<E>(d, c, dn);
+    stv<E>(res, c, r);
+  }
+  __device__ void one(int64_t c) {
+    d[c] = (first ? T(0) : d[c]) + (alpha * p[c] + omega * s[c]);
+    const T r = s[c] - omega * t[c];
     res[c] = r;
-    acc += (double)hv[u] * (double)r;
+    acc += (double)rhat[c] * (double)r;
   }
 };
 
@@ -621,7 +849,8 @@ __global__ __launch_bounds__(kBlock) void k_bicg_update(const BlockEnt *tab, con
                                                         double *part) {
   PI_PROLOGUE
   if (skip_inner(in, st)) return;
-  const Walk wk = make_walk(in, e.lb);
+  int64_t beg, end;
+  linear_range(in, e.lb, beg, end);
   BicgUpdate<T> f;
   f.p = gp<T>(in.p[st->pcur]);
   f.s = gp<T>(in.bs[2]);
@@ -633,7 +862,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg_update(const BlockEnt *tab, con
   f.omega = (T)st->omega;
   f.first = st->inner == 0;
   f.acc = 0.0;
-  stream(wk, f);
+  stream_linear<BicgUpdate<T>::E, BicgUpdate<T>::U>(beg, end, f);
   double acc[1] = {f.acc};
   publish<1>(in, part, e.lb, acc);
 }
@@ -644,13 +873,11 @@ __global__ __launch_bounds__(kBlock) void k_copy_res(const BlockEnt *tab, const 
                                                      double *part) {
   PI_PROLOGUE
   if (skip_outer(st)) return;
-  const Walk wk = make_walk(in, e.lb);
+  int64_t beg, end;
+  linear_range(in, e.lb, beg, end);
   const T *res = (const T *)in.res;
   T *rhat = (T *)in.bs[0];
-  if (wk.act) {
-    int64_t c = wk.base + (int64_t)wk.m0 * wk.sm;
-    for (int m = wk.m0; m < wk.m1; ++m, c += wk.sm) rhat[c] = res[c];
-  }
+  for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) rhat[c] = res[c];
 }
 
 // ---------------------------------------------------------------------------
@@ -673,13 +900,12 @@ __global__ __launch_bounds__(kBlock) void k_gauge_sum(const BlockEnt *tab, const
     }
     return;
   }
-  const Walk wk = make_walk(in, e.lb);
+  int64_t beg, end;
+  linear_range(in, e.lb, beg, end);
+  const uint32_t *code = in.code;
   double acc[1] = {0.0};
-  if (wk.act) {
-    int64_t c = wk.base + (int64_t)wk.m0 * wk.sm;
-    for (int m = wk.m0; m < wk.m1; ++m, c += wk.sm)
-      if (wk.code[c] & kValidBit) acc[0] += P[c];
-  }
+  for (int64_t c = beg + threadIdx.x; c < end; c += kBlock)
+    if (code[c] & kValidBit) acc[0] += P[c];
   publish<1>(in, part, e.lb, acc);
 }
 
@@ -698,28 +924,27 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gauge_apply(const BlockEnt *tab, const Inst *insts, State *sts,
                                                         double *part) {
   PI_PROLOGUE
-  const Walk wk = make_walk(in, e.lb);
+  int64_t beg, end;
+  linear_range(in, e.lb, beg, end);
   const double *P = in.P[st->Pcur];
+  const uint32_t *code = in.code;
   T *out = (T *)in.Pout;
   const bool zero = st->normS2 == 0.0;
   const double mean1 = st->red[0] * in.inv_nvalid;
-  if (wk.act) {
-    int64_t c = wk.base + (int64_t)wk.m0 * wk.sm;
-    for (int m = wk.m0; m < wk.m1; ++m, c += wk.sm) {
-      T v;
-      if (wk.code[c] & kValidBit) {
-        if (zero) {
-          v = T(0);
-        } else if (in.ncomp > 1) {
-          v = (T)(P[c] - in.comp_sum[in.label[c]]);
-        } else {
-          v = (T)(P[c] - mean1);
-        }
+  for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
+    T v;
+    if (code[c] & kValidBit) {
+      if (zero) {
+        v = T(0);
+      } else if (in.ncomp > 1) {
+        v = (T)(P[c] - in.comp_sum[in.label[c]]);
       } else {
-        v = (T)NAN;
+        v = (T)(P[c] - mean1);
       }
-      out[c] = v;
+    } else {
+      v = (T)NAN;
     }
+    out[c] = v;
   }
 }
 
@@ -783,6 +1008,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
         st->outer += 1;
         st->rr = s[1];
         st->inner = 0;
+        st->tail = 0;
         st->first = 1;
         st->beta = 0.0;  // the first search direction is the residual itself
         st->have_delta = 1;
@@ -797,6 +1023,12 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
       st->alpha = s[0] != 0.0 ? st->rr / s[0] : 0.0;
       st->pcur ^= 1;
       st->first = 0;
+      if (st->inner + 1 >= in.inner_iters) {
+        // last inner iteration: its update is left to the outer kernel
+        st->tail = 1;
+        st->inner += 1;
+        st->inner_total += 1;
+      }
       break;
     case K_CG_UPDATE:
       st->beta = st->rr != 0.0 ? s[0] / st->rr : 0.0;
@@ -830,7 +1062,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
 // ---------------------------------------------------------------------------
 // plain operator applies (pi_apply): y = M x, N x or (M - N) x
 // ---------------------------------------------------------------------------
-template <typename T, int ND>
+template <typename T, int ND, int W, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Inst *insts, State *sts, double *part,
                                                   int op, const T *x_, T *y_) {
   PI_PROLOGUE
@@ -840,13 +1072,15 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Ins
   __shared__ T lut_b[6][kStates];
   load_lut<T>(in.lut_np1, lut_a);
   load_lut<T>(in.lut_n, lut_b);
-  const Walk wk = make_walk(in, e.lb);
+  const Walk wk = make_walk<W>(in, e.lb);
   T a[6];
 #pragma unroll
   for (int d = 0; d < 6; ++d) a[d] = (T)in.a[d];
   const int bits = dir_bits(ND);
-  auto load = [&](int64_t c) -> T { return x[c]; };
-  auto body = [&](int64_t c, const Plane<T, int> &pl, T vW, T vE, T vP, T vN) -> T {
+  auto load = [&](int64_t c) { return ldv<W>(x, c); };
+  auto load1 = [&](int64_t c) -> T { return x[c]; };
+  auto aux = [](int64_t) { return Vec<int, W>{}; };
+  auto body = [&](int64_t, const Cell<T, int> &pl, T vW, T vE, T vP, T vN) -> T {
     const uint32_t cd = pl.code;
     const T vC = pl.v;
     if (!(cd & kValidBit)) return T(0);
@@ -889,8 +1123,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Ins
     }
     return s;
   };
-  auto store = [&](int64_t c, const T &v) { y[c] = v; };
-  march<ND, T, int, T>(wk, load, [](int64_t) { return 0; }, body, store);
+  auto store = [&](int64_t c, const T (&o)[W]) {
+    Vec<T, W> v;
+#pragma unroll
+    for (int k = 0; k < W; ++k) v.e[k] = o[k];
+    stv<W>(y, c, v);
+  };
+  march<ND, W, GEN, T, int, T>(wk, load, load1, aux, body, store);
 }
 
 // ---------------------------------------------------------------------------
@@ -898,8 +1137,24 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Ins
 // ---------------------------------------------------------------------------
 #define PI_ARGS tab, insts, sts, part
 
+// stencil kernels come in eight shapes (see shape_of)
+#define PI_MARCH(KERN, ...)                                                               \
+  do {                                                                                    \
+    switch (shape) {                                                                      \
+      case 0: KERN<T, 2, 1, false><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
+      case 1: KERN<T, 3, 1, false><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
+      case 2: KERN<T, 2, 4, false><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
+      case 3: KERN<T, 3, 4, false><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
+      case 4: KERN<T, 2, 1, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;             \
+      case 5: KERN<T, 3, 1, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;             \
+      case 6: KERN<T, 2, 4, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;             \
+      default: KERN<T, 3, 4, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
+    }                                                                                     \
+  } while (0)
+
 template <typename T>
-static hipError_t launch_t(KernelId k, int ndim, const LaunchArgs &la) {
+static hipError_t launch_t(KernelId k, int shape, const LaunchArgs &la) {
+  const int ndim = (shape & 1) ? 3 : 2;
   const dim3 grid(la.nblocks), block(kBlock);
   const BlockEnt *tab = la.tab;
   const Inst *insts = la.insts;
@@ -912,42 +1167,25 @@ static hipError_t launch_t(KernelId k, int ndim, const LaunchArgs &la) {
       if (ndim == 3) k_source<T, 3><<<grid, block, 0, s>>>(PI_ARGS);
       else k_source<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
       break;
-    case K_OUTER:
-      if (ndim == 3) k_outer<T, 3><<<grid, block, 0, s>>>(PI_ARGS);
-      else k_outer<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
-      break;
-    case K_CG_SPMV:
-      if (ndim == 3) k_cg_spmv<T, 3><<<grid, block, 0, s>>>(PI_ARGS);
-      else k_cg_spmv<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
-      break;
+    case K_OUTER: PI_MARCH(k_outer, PI_ARGS); break;
+    case K_CG_SPMV: PI_MARCH(k_cg_spmv, PI_ARGS); break;
     case K_CG_UPDATE: k_cg_update<T><<<grid, block, 0, s>>>(PI_ARGS); break;
-    case K_BICG_P:
-      if (ndim == 3) k_bicg_spmv_p<T, 3><<<grid, block, 0, s>>>(PI_ARGS);
-      else k_bicg_spmv_p<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
-      break;
-    case K_BICG_S:
-      if (ndim == 3) k_bicg_spmv_s<T, 3><<<grid, block, 0, s>>>(PI_ARGS);
-      else k_bicg_spmv_s<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
-      break;
+    case K_BICG_P: PI_MARCH(k_bicg_spmv_p, PI_ARGS); break;
+    case K_BICG_S: PI_MARCH(k_bicg_spmv_s, PI_ARGS); break;
     case K_BICG_UPDATE: k_bicg_update<T><<<grid, block, 0, s>>>(PI_ARGS); break;
     case K_COPY_RES: k_copy_res<T><<<grid, block, 0, s>>>(PI_ARGS); break;
     case K_GAUGE_GROUPS: k_gauge_groups<<<grid, block, 0, s>>>(PI_ARGS); break;
     case K_GAUGE_SUM: k_gauge_sum<<<grid, block, 0, s>>>(PI_ARGS); break;
     case K_GAUGE_APPLY: k_gauge_apply<T><<<grid, block, 0, s>>>(PI_ARGS); break;
-    case K_APPLY:
-      if (ndim == 3)
-        k_apply<T, 3><<<grid, block, 0, s>>>(PI_ARGS, la.iarg, (const T *)la.x, (T *)la.y);
-      else
-        k_apply<T, 2><<<grid, block, 0, s>>>(PI_ARGS, la.iarg, (const T *)la.x, (T *)la.y);
-      break;
+    case K_APPLY: PI_MARCH(k_apply, PI_ARGS, la.iarg, (const T *)la.x, (T *)la.y); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch(KernelId k, bool fp64, int ndim, const LaunchArgs &la) {
+hipError_t launch(KernelId k, bool fp64, int shape, const LaunchArgs &la) {
   if (la.nblocks <= 0) return hipSuccess;
-  return fp64 ? launch_t<double>(k, ndim, la) : launch_t<float>(k, ndim, la);
+  return fp64 ? launch_t<double>(k, shape, la) : launch_t<float>(k, shape, la);
 }
 
 bool reduces(KernelId k) {

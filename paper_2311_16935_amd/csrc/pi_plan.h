@@ -60,7 +60,7 @@ namespace pi {
 hipError_t plan_alloc(pi_plan_s *p, void **ptr, size_t bytes);
 
 // Geometry of the strip decomposition for one grid (fields of Inst).
-void set_walk(Inst &in, int ndim, const int64_t dims[3], int mseg_override);
+void set_walk(Inst &in, int ndim, const int64_t dims[3], int mseg_override, int vw_override);
 
 // Single-instance table and partial slots of a plan.
 hipError_t plan_tables(pi_plan_s *p);

@@ -242,13 +242,17 @@ static void fill_luts(pi_plan_s *p, Inst &in) {
   }
 }
 
-void set_walk(Inst &in, int ndim, const int64_t dims[3], int mseg_override) {
+void set_walk(Inst &in, int ndim, const int64_t dims[3], int mseg_override, int vw_override) {
   in.ndim = ndim;
   in.nx = (int32_t)dims[0];
   in.ny = (int32_t)dims[1];
   in.nz = ndim == 3 ? (int32_t)dims[2] : 1;
   in.ncell = (int64_t)in.nx * in.ny * in.nz;
-  in.nxs = (in.nx + kWave - 1) / kWave;
+  // four cells per lane (16-byte accesses) need rows that start 16-byte aligned
+  const bool can4 = in.nx % 4 == 0;
+  in.vw = vw_override == 1 ? 1 : (can4 ? 4 : 1);
+  const int strip = kWave * in.vw;
+  in.nxs = (in.nx + strip - 1) / strip;
   int64_t strips;
   if (ndim == 3) {
     in.rows = in.ny;
@@ -265,13 +269,10 @@ void set_walk(Inst &in, int ndim, const int64_t dims[3], int mseg_override) {
   }
   int mseg = mseg_override;
   if (mseg <= 0) {
-    // about one occupancy round of waves (8 per SIMD on 256 CUs), with
-    // segments a multiple of the streaming depth
+    // about one occupancy round of waves (8 per SIMD on 256 CUs)
     const int64_t target_waves = 8192;
     const int64_t nseg_t = std::max<int64_t>(1, target_waves / std::max<int64_t>(1, strips));
-    const int step = kStream;
-    mseg = (int)std::max<int64_t>(step, (in.nm + nseg_t - 1) / nseg_t);
-    mseg = (mseg + step - 1) / step * step;
+    mseg = (int)std::max<int64_t>(4, (in.nm + nseg_t - 1) / nseg_t);
   }
   mseg = std::max(1, std::min(mseg, in.nm));
   in.mseg = mseg;
@@ -443,7 +444,8 @@ extern "C" pi_status pi_plan(int ndim, const int64_t dims[3], const double spaci
   const size_t N = (size_t)ncell;
   Inst &in = p->inst;
   memset(&in, 0, sizeof(in));
-  set_walk(in, ndim, p->dims, 0);
+  set_walk(in, ndim, p->dims, 0, 0);
+  in.gen = mask ? 0 : 1;
   fill_luts(p, in);
   in.ncomp = p->ncomp;
   in.inv_nvalid = 1.0 / (double)nvalid;
@@ -571,9 +573,10 @@ extern "C" void pi_plan_destroy(pi_plan_t p) {
 
 extern "C" size_t pi_workspace_bytes(pi_plan_t p) { return p ? p->bytes : 0; }
 
-extern "C" pi_status pi_set_tile(pi_plan_t p, int32_t mseg) {
-  if (!p || mseg < 0) return PI_ERR_INVALID_ARG;
-  set_walk(p->inst, p->ndim, p->dims, mseg);
+extern "C" pi_status pi_set_tile(pi_plan_t p, int32_t mseg, int32_t lane_cells) {
+  if (!p || mseg < 0 || (lane_cells != 0 && lane_cells != 1 && lane_cells != 4)) return PI_ERR_INVALID_ARG;
+  if (lane_cells == 4 && p->dims[0] % 4 != 0) return PI_ERR_INVALID_ARG;
+  set_walk(p->inst, p->ndim, p->dims, mseg, lane_cells);
   if (plan_tables(p) != hipSuccess) return PI_ERR_OOM;
   if (hipMemcpy(p->d_inst, &p->inst, sizeof(Inst), hipMemcpyHostToDevice) != hipSuccess) return PI_ERR_DEVICE;
   if (p->graph) (void)hipGraphExecDestroy(p->graph);
@@ -583,6 +586,8 @@ extern "C" pi_status pi_set_tile(pi_plan_t p, int32_t mseg) {
 }
 
 extern "C" int32_t pi_get_tile(pi_plan_t p) { return p ? p->inst.mseg : 0; }
+
+extern "C" int32_t pi_get_lane_cells(pi_plan_t p) { return p ? p->inst.vw : 0; }
 
 extern "C" pi_status pi_set_inner_iters(pi_plan_t p, int32_t iters) {
   if (!p || iters < 1 || iters > 4096) return PI_ERR_INVALID_ARG;

@@ -27,7 +27,7 @@ namespace {
 
 constexpr int kUnroll = 8;  // outer steps per graph replay
 
-struct Group {               // instances of one dimensionality
+struct Group {               // instances of one launch shape (shape_of)
   BlockEnt *tab = nullptr;   // device
   int ntab = 0;
 };
@@ -38,15 +38,15 @@ struct Launcher {
   State *sts = nullptr;
   double *part = nullptr;
   int count = 0;             // instances
-  Group grp[2];              // [0] = 2-D, [1] = 3-D
+  Group grp[kShapes];
 
   // the kernel over every instance, then (if it reduces) its finalize
   hipError_t go(KernelId k, hipStream_t s, int iarg = 0, const void *x = nullptr, void *y = nullptr,
                 bool finalize = true) const {
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < kShapes; ++g) {
       if (grp[g].ntab <= 0) continue;
       LaunchArgs la{grp[g].tab, insts, sts, part, grp[g].ntab, s, iarg, x, y};
-      hipError_t e = launch(k, fp64, g == 0 ? 2 : 3, la);
+      hipError_t e = launch(k, fp64, g, la);
       if (e != hipSuccess) return e;
     }
     if (finalize && reduces(k)) return launch_finalize(k, insts, sts, part, count, s);
@@ -64,8 +64,9 @@ struct Launcher {
           if ((e = go(K_BICG_S, s)) != hipSuccess) return e;
           if ((e = go(K_BICG_UPDATE, s)) != hipSuccess) return e;
         } else {
+          // the last iteration's update is folded into the next outer kernel
           if ((e = go(K_CG_SPMV, s)) != hipSuccess) return e;
-          if ((e = go(K_CG_UPDATE, s)) != hipSuccess) return e;
+          if (i + 1 < inner && (e = go(K_CG_UPDATE, s)) != hipSuccess) return e;
         }
       }
     }
@@ -209,7 +210,7 @@ Launcher single_launcher(pi_plan_s *p) {
   L.sts = p->d_state;
   L.part = p->d_part;
   L.count = 1;
-  L.grp[p->ndim == 3 ? 1 : 0] = Group{p->d_tab, p->ntab};
+  L.grp[shape_of(p->ndim, p->inst.vw, p->inst.gen)] = Group{p->d_tab, p->ntab};
   return L;
 }
 
@@ -266,17 +267,17 @@ extern "C" pi_status pi_solve_batched(int64_t count, const pi_plan_t *plans, con
       return PI_ERR_INVALID_ARG;
     inner = std::max(inner, p->inner_iters);
   }
-  // block tables per dimensionality; partial slots are numbered across both
-  std::vector<Inst *> by[2];
-  std::vector<int64_t> idx[2];
+  // block tables per launch shape; partial slots are numbered across all
+  std::vector<Inst *> by[kShapes];
+  std::vector<int64_t> idx[kShapes];
   for (int64_t i = 0; i < count; ++i) {
-    const int g = host[i].ndim == 3 ? 1 : 0;
+    const int g = shape_of(host[i].ndim, host[i].vw, host[i].gen);
     by[g].push_back(&host[i]);
     idx[g].push_back(i);
   }
-  std::vector<BlockEnt> tabs[2];
+  std::vector<BlockEnt> tabs[kShapes];
   int parts = 0;
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < kShapes; ++g) {
     if (by[g].empty()) continue;
     int total = 0;
     tabs[g] = build_table(by[g], parts, &total);
@@ -300,7 +301,7 @@ extern "C" pi_status pi_solve_batched(int64_t count, const pi_plan_t *plans, con
     rc = PI_ERR_OOM;
     goto done;
   }
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < kShapes; ++g) {
     if (tabs[g].empty()) continue;
     if (hipMalloc((void **)&L.grp[g].tab, tabs[g].size() * sizeof(BlockEnt)) != hipSuccess) {
       rc = PI_ERR_OOM;
@@ -338,7 +339,7 @@ done:
   if (L.insts) (void)hipFree(L.insts);
   if (L.sts) (void)hipFree(L.sts);
   if (L.part) (void)hipFree(L.part);
-  for (int g = 0; g < 2; ++g)
+  for (int g = 0; g < kShapes; ++g)
     if (L.grp[g].tab) (void)hipFree(L.grp[g].tab);
   if (hst) (void)hipHostFree(hst);
   return rc;
@@ -365,6 +366,8 @@ extern "C" pi_status pi_source(pi_plan_t p, const void *gx, const void *gy, cons
 
 extern "C" pi_status pi_apply(pi_plan_t p, int op, const void *x, void *y, void *stream_) {
   if (!p || !x || !y || op < PI_OP_M || op > PI_OP_L || x == y) return PI_ERR_INVALID_ARG;
+  // four cells per lane move 16-byte vectors
+  if (p->inst.vw == 4 && (((uintptr_t)x | (uintptr_t)y) & 15u) != 0) return PI_ERR_INVALID_ARG;
   hipStream_t stream = (hipStream_t)stream_;
   // the operator reads only plan fields of the device instance record, which
   // every call leaves in place
@@ -417,44 +420,47 @@ out:
   return rc;
 }
 
-// tile cache of pi_autotune: (ndim, nx, ny, nz, fp64, bicgstab) -> mseg
+// tile cache of pi_autotune: (ndim, nx, ny, nz, fp64, bicgstab) -> (mseg, lane cells)
 static std::mutex g_tune_mu;
-static std::map<std::array<int64_t, 6>, int32_t> g_tune;
+static std::map<std::array<int64_t, 6>, std::array<int32_t, 2>> g_tune;
 
 extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, void *stream) {
   if (!p || reps < 1) return PI_ERR_INVALID_ARG;
   const std::array<int64_t, 6> key = {p->ndim, p->dims[0], p->dims[1], p->dims[2], p->fp64, p->bicgstab};
-  int32_t best = -1;
+  std::array<int32_t, 2> best = {-1, 0};
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune.find(key);
     if (it != g_tune.end()) best = it->second;
   }
-  if (best < 0) {
-    pi_status rc = pi_set_tile(p, 0);
-    if (rc != PI_OK) return rc;
-    std::vector<int32_t> cand = {p->inst.mseg};
-    for (int32_t m = kStream; m <= 256; m *= 2)
-      if (m < p->inst.nm && std::find(cand.begin(), cand.end(), m) == cand.end()) cand.push_back(m);
+  pi_status rc;
+  if (best[0] < 0) {
+    std::vector<std::array<int32_t, 2>> cand;
+    const std::vector<int32_t> widths = p->dims[0] % 4 == 0 ? std::vector<int32_t>{4, 1} : std::vector<int32_t>{1};
+    for (int32_t vw : widths) {
+      if ((rc = pi_set_tile(p, 0, vw)) != PI_OK) return rc;
+      cand.push_back({p->inst.mseg, vw});
+      for (int32_t m = 2; m <= 256; m *= 2)
+        if (m < p->inst.nm && m != p->inst.mseg) cand.push_back({m, vw});
+    }
     double best_ms = 1e300;
-    for (int32_t m : cand) {
-      rc = pi_set_tile(p, m);
-      if (rc != PI_OK) return rc;
+    for (const auto &c : cand) {
+      if ((rc = pi_set_tile(p, c[0], c[1])) != PI_OK) return rc;
       double t_outer = 0.0, t_spmv = 0.0, t_upd = 0.0;
       if ((rc = pi_time_kernel(p, PI_K_OUTER, reps, &t_outer, stream)) != PI_OK ||
           (rc = pi_time_kernel(p, PI_K_SPMV, reps, &t_spmv, stream)) != PI_OK ||
           (rc = pi_time_kernel(p, PI_K_UPDATE, reps, &t_upd, stream)) != PI_OK)
         return rc;
-      const double step = t_outer + p->inner_iters * (t_spmv + t_upd);
+      const double step = t_outer + p->inner_iters * t_spmv + (p->inner_iters - 1) * t_upd;
       if (step < best_ms) {
         best_ms = step;
-        best = p->inst.mseg;
+        best = {p->inst.mseg, p->inst.vw};
       }
     }
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[key] = best;
   }
-  pi_status rc = pi_set_tile(p, best);
+  rc = pi_set_tile(p, best[0], best[1]);
   if (rc == PI_OK && mseg_out) *mseg_out = p->inst.mseg;
   return rc;
 }

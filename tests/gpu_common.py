@@ -41,6 +41,8 @@ def fp64_cases():
         ("3d_aniso_masked_24x17x13", lambda: synth.random_small(42, 3, (24, 17, 13), mask_frac=0.1)),
         ("3d_iso_masked_70x21x9", lambda: synth.random_small(43, 3, (70, 21, 9), anisotropic=False,
                                                              mask_frac=0.1)),
+        ("3d_iso_unmasked_32x20x12", lambda: synth.random_small(45, 3, (32, 20, 12), anisotropic=False,
+                                                                mask_frac=0.0)),
     ]
 
 
@@ -52,6 +54,8 @@ def fp32_cases():
         ("3d_aniso_masked_70x37x29", lambda: synth.random_small(13, 3, (70, 37, 29), mask_frac=0.1)),
         ("3d_iso_masked_33x65x17", lambda: synth.random_small(14, 3, (33, 65, 17), anisotropic=False,
                                                               mask_frac=0.1)),
+        ("3d_aniso_unmasked_48x24x20", lambda: synth.random_small(15, 3, (48, 24, 20), mask_frac=0.0)),
+        ("2d_aniso_unmasked_132x90", lambda: synth.random_small(16, 2, (132, 90), mask_frac=0.0)),
     ]
 
 
