@@ -60,6 +60,8 @@ def parse():
                                                       "unet_blobs64.safetensors"),
                     help="trained warm-start network; the warm-started solve is skipped if missing")
     ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--no-variant", action="store_true",
+                    help="skip the fixed-point CG variant (not the paper's iteration), reported beside it")
     return ap.parse_args()
 
 
@@ -191,6 +193,49 @@ def warm_start_leg(args, pi, plan, grads, P_plain, n):
             "maxabs_vs_plain_rel_rms": diff}
 
 
+def variant_leg(args, pi, grads, P_plain, n, spacing, weights_ok):
+    """The PI_FIXED_POINT_CG variant -- CG on the fixed point's operator
+    instead of the paper's lagged boundary iteration, same stopping test and
+    converged field -- from zero and from the learned guess."""
+    import torch
+
+    plan = pi.Plan((n, n, n), spacing, fixed_point=True)
+    plan.autotune(reps=5)
+    P = torch.empty_like(P_plain)
+    out = {"inner_per_outer": None}
+    for i in range(args.warmup):
+        r = plan.solve(grads, P=P, tol=args.tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = plan.solve(grads, P=P, tol=args.tol)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / max(1, args.steps)
+    info = r.info
+    assert info["status"] == 0 and info["eps_R"] <= args.tol, info
+    rms = float(P_plain.double().pow(2).mean().sqrt())
+    out.update({"s_per_solve": sec, "outer_iters": info["outer_iters"], "inner_iters": info["inner_iters_total"],
+                "eps_R": info["eps_R"], "inner_per_outer": info["inner_iters_total"] // max(1, info["outer_iters"]),
+                "maxabs_vs_plain_rel_rms": float((P.double() - P_plain.double()).abs().max()) / rms})
+    progress(f"fixed-point CG variant: {sec:.3f} s per solve, {info['inner_iters_total']} CG iterations")
+    if weights_ok:
+        from paper_2311_16935_amd.warmstart import UNet, WarmStart
+
+        net = UNet.from_file(args.weights)
+        ws = WarmStart(net, n // int(net.meta.get("train_n", 64)))
+        ws.solve(plan, grads, P=P, tol=args.tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            r = ws.solve(plan, grads, P=P, tol=args.tol)
+        torch.cuda.synchronize()
+        wsec = (time.perf_counter() - t0) / max(1, args.steps)
+        out.update({"warm_s_per_solve": wsec, "warm_inner_iters": r.info["inner_iters_total"]})
+        progress(f"fixed-point CG variant from the learned guess: {wsec:.3f} s per solve")
+    plan.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -237,8 +282,12 @@ def main():
     assert info["status"] == 0 and info["eps_R"] <= args.tol, info
     P_plain = P.clone()
     warm = None
-    if not args.no_warm and os.path.exists(args.weights):
+    weights_ok = not args.no_warm and os.path.exists(args.weights)
+    if weights_ok:
         warm = warm_start_leg(args, pi, plan, grads, P_plain, n)
+    variant = None
+    if not args.no_variant:
+        variant = variant_leg(args, pi, grads, P_plain, n, w.spacing, weights_ok)
 
     # kernel durations, measured with HIP events on the library's stream
     src_hash = kernel_source_hash()
@@ -282,6 +331,7 @@ def main():
                   "outer_point_iters_per_s": ncell * info["outer_iters"] / sec,
                   "inner_point_iters_per_s": ncell * info["inner_iters_total"] / sec},
         "warm_start": warm,
+        "variant_fixed_point_cg": variant,
         "autotune": tune,
         "roofline": roof,
         "kernels": kern,

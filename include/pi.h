@@ -56,6 +56,15 @@ typedef struct pi_plan_s *pi_plan_t;
 #define PI_FP64 0x1u
 #define PI_INNER_CG 0x0u        /* conjugate gradient, as in the paper's GPU code */
 #define PI_INNER_BICGSTAB 0x2u  /* stabilised BiCG, safe for the nonsymmetric M  */
+/*
+ * Variant, not the paper's iteration: solve the fixed point of Eq.
+ * MatrixEquation, ([W^{n+1}] - [W^n]) P = S, directly -- CG on that
+ * symmetric operator for the inner correction instead of [W^{n+1}], so the
+ * boundary rows are no longer lagged by one outer step.  Same FP64 outer
+ * residual, same stopping test (Eq. ResidualMomentum) and same converged
+ * field; far fewer passes over the grid.  CG only (not with BiCGStab).
+ */
+#define PI_FIXED_POINT_CG 0x4u
 
 /* pi_solve flags */
 #define PI_WARM_START 0x1u      /* P holds P^0 on entry (else P^0 = 0)            */
@@ -87,7 +96,8 @@ typedef struct pi_info {
  *   spacing  host array {dx, dy, dz}, finite and > 0 (dz ignored in 2-D).
  *   mask     host pointer to nx*ny*nz bytes (copied), or NULL = all cells hold
  *            data.  At least one cell must hold data.
- *   flags    PI_FP32 or PI_FP64, ORed with PI_INNER_CG or PI_INNER_BICGSTAB.
+ *   flags    PI_FP32 or PI_FP64, ORed with PI_INNER_CG or PI_INNER_BICGSTAB,
+ *            optionally ORed with PI_FIXED_POINT_CG (with PI_INNER_CG only).
  *   out      receives the plan; set to NULL on failure.
  * Errors: PI_ERR_INVALID_ARG, PI_ERR_OOM, PI_ERR_DEVICE.  Synchronous.
  */

@@ -67,6 +67,7 @@ struct Inst {
   int32_t part_base;// first slot of this instance in the partial-sum array
   int32_t ncomp;    // connected groups of data cells
   int32_t inner_iters; // inner Krylov iterations per outer step
+  int32_t inner_op; // operator of the inner solve: 0 [W^{n+1}], 1 [W^{n+1}] - [W^n]
   double inv_nvalid;// 1 / data cells (gauge of a single group)
   double a[6];      // per-direction face total / A_tot
   double dsig[6];   // signed spacing Delta_j

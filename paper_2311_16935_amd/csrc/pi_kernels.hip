@@ -586,7 +586,27 @@ __device__ inline T apply_m(const T (*lut)[kStates], uint32_t cd, int bits, T vC
   return s;
 }
 
-// p <- r + beta p (or p <- r on the first iteration), q <- M p, p.q
+// The fixed point's operator [W^{n+1}] - [W^n]: sum_j a_j (v_C - v_J) over
+// face neighbours holding data (the PI_FIXED_POINT_CG variant's inner operator).
+template <typename T, int ND>
+__device__ inline T apply_l(const T *a, uint32_t cd, int bits, T vC, T vW, T vE, T vN, T vS, T vP, T vNx) {
+  T s = T(0);
+  if (dstate(cd, DE, bits)) s += a[DE] * (vC - vE);
+  if (dstate(cd, DW, bits)) s += a[DW] * (vC - vW);
+  if (ND == 3) {
+    if (dstate(cd, DN, bits)) s += a[DN] * (vC - vN);
+    if (dstate(cd, DS, bits)) s += a[DS] * (vC - vS);
+    if (dstate(cd, DF, bits)) s += a[DF] * (vC - vNx);
+    if (dstate(cd, DB, bits)) s += a[DB] * (vC - vP);
+  } else {
+    if (dstate(cd, DN, bits)) s += a[DN] * (vC - vNx);
+    if (dstate(cd, DS, bits)) s += a[DS] * (vC - vP);
+  }
+  return s;
+}
+
+// p <- r + beta p (or p <- r on the first iteration), q <- A p, p.q with A
+// the inner operator ([W^{n+1}], or the fixed point's for the variant)
 template <typename T, int ND, int W, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_cg_spmv(const BlockEnt *tab, const Inst *insts, State *sts,
                                                     double *part) {
@@ -604,6 +624,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const BlockEnt *tab, const I
   const PI_G T *res = gp<T>(in.res);
   PI_G T *q = gp<T>(in.q);
   const int bits = dir_bits(ND);
+  const bool opL = in.inner_op != 0;  // uniform over the launch
+  T a[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) a[d] = (T)in.a[d];
   double acc[1] = {0.0};
   struct Out {
     T p, q;
@@ -621,7 +645,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const BlockEnt *tab, const I
     const uint32_t cd = pl.code;
     const T vC = pl.v;
     if (!(cd & kValidBit)) return Out{T(0), T(0)};
-    const T s = apply_m<T, ND>(lut, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN);
+    const T s = opL ? apply_l<T, ND>(a, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN)
+                    : apply_m<T, ND>(lut, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN);
     acc[0] += (double)vC * (double)s;
     return Out{vC, s};
   };
@@ -1035,6 +1060,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
       st->rr = s[0];
       st->inner += 1;
       st->inner_total += 1;
+      // fixed-point variant: the inner residual is the outer residual of
+      // P + d, so the inner solve stops once it is well below the tolerance
+      // (the FP64 outer step then confirms it)
+      if (in.inner_op != 0 && s[0] <= 0.25 * in.tol * in.tol * st->normS2) st->inner = in.inner_iters;
       break;
     case K_BICG_P:
       st->alpha = s[0] != 0.0 ? st->rho / s[0] : 0.0;

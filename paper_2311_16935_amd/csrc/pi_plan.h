@@ -15,6 +15,7 @@ struct pi_plan_s {
   uint32_t flags = 0;
   bool fp64 = false;
   bool bicgstab = false;
+  bool fixed_point = false;  // PI_FIXED_POINT_CG variant
   int inner_iters = 4;
   int64_t ncell = 0;
   int64_t nvalid = 0;

@@ -394,7 +394,8 @@ extern "C" pi_status pi_plan(int ndim, const int64_t dims[3], const double spaci
   if (!out) return PI_ERR_INVALID_ARG;
   *out = nullptr;
   if ((ndim != 2 && ndim != 3) || !dims || !spacing) return PI_ERR_INVALID_ARG;
-  if (flags & ~(PI_FP64 | PI_INNER_BICGSTAB)) return PI_ERR_INVALID_ARG;
+  if (flags & ~(PI_FP64 | PI_INNER_BICGSTAB | PI_FIXED_POINT_CG)) return PI_ERR_INVALID_ARG;
+  if ((flags & PI_FIXED_POINT_CG) && (flags & PI_INNER_BICGSTAB)) return PI_ERR_INVALID_ARG;
   int64_t ncell = 1;
   for (int a = 0; a < ndim; ++a) {
     if (dims[a] < 1 || dims[a] >= (int64_t(1) << 31)) return PI_ERR_INVALID_ARG;
@@ -412,6 +413,7 @@ extern "C" pi_status pi_plan(int ndim, const int64_t dims[3], const double spaci
   p->flags = flags;
   p->fp64 = (flags & PI_FP64) != 0;
   p->bicgstab = (flags & PI_INNER_BICGSTAB) != 0;
+  p->fixed_point = (flags & PI_FIXED_POINT_CG) != 0;
   p->ncell = ncell;
   // inner iterations per outer step.  The outer step count falls towards its
   // exact-inner limit (about 16 times the longest side) as k grows, while an
@@ -424,6 +426,10 @@ extern "C" pi_status pi_plan(int ndim, const int64_t dims[3], const double spaci
     int lg = 0;
     while ((int64_t(1) << lg) < L) ++lg;
     p->inner_iters = ndim == 3 ? std::min(24, std::max(4, 3 * lg - 12)) : std::min(32, std::max(4, 4 * lg - 24));
+    // the fixed-point variant restarts CG once per outer step and stops it
+    // early once the tolerance is met: a restart length of a few times the
+    // longest side lets one or two outer steps do
+    if (p->fixed_point) p->inner_iters = (int)std::min<int64_t>(4096, std::max<int64_t>(32, 4 * L));
   }
 
   // data cells and their connected groups
@@ -455,6 +461,7 @@ extern "C" pi_status pi_plan(int ndim, const int64_t dims[3], const double spaci
   memset(&in, 0, sizeof(in));
   set_walk(in, ndim, p->dims, 0, 0);
   in.gen = mask ? 0 : 1;
+  in.inner_op = p->fixed_point ? 1 : 0;
   fill_luts(p, in);
   in.ncomp = p->ncomp;
   in.inv_nvalid = 1.0 / (double)nvalid;

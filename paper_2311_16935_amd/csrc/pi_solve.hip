@@ -74,11 +74,14 @@ struct Launcher {
   }
 };
 
+// outer steps per graph replay: about kUnroll * 8 inner iterations
+int unroll_for(int inner) { return std::max(1, std::min(kUnroll, 64 / std::max(1, inner))); }
+
 hipError_t capture(const Launcher &L, hipStream_t cap, int inner, bool bicg, hipGraphExec_t *exec) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
-  hipError_t e2 = L.outer_steps(cap, kUnroll, inner, bicg);
+  hipError_t e2 = L.outer_steps(cap, unroll_for(inner), inner, bicg);
   e = hipStreamEndCapture(cap, &g);
   if (e2 != hipSuccess) e = e2;
   if (e != hipSuccess) {
@@ -102,15 +105,15 @@ State fresh_state() {
 // Replay the outer-step graph until every instance reports done.  `hstate`
 // is a pinned buffer of 2 * count records.
 pi_status iterate(hipGraphExec_t exec, hipStream_t stream, State *dstate, State *hstate, int64_t count,
-                  int64_t max_iter) {
+                  int64_t max_iter, int unroll) {
   hipEvent_t ev[2];
   if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess) return PI_ERR_DEVICE;
   if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
     (void)hipEventDestroy(ev[0]);
     return PI_ERR_DEVICE;
   }
-  // every replay advances each unfinished instance by kUnroll outer steps
-  const int64_t bound = max_iter / kUnroll + 4;
+  // every replay advances each unfinished instance by `unroll` outer steps
+  const int64_t bound = max_iter / unroll + 4;
   int64_t launched = 0;
   int replays = 1;
   int cur = 0;
@@ -238,7 +241,7 @@ extern "C" pi_status pi_solve(pi_plan_t p, const void *gx, const void *gy, const
     p->graph_key = key;
   }
   // h_state holds three records: [0] final snapshot, [1..2] polling buffers
-  pi_status rc = iterate(p->graph, stream, p->d_state, p->h_state + 1, 1, max_iter);
+  pi_status rc = iterate(p->graph, stream, p->d_state, p->h_state + 1, 1, max_iter, unroll_for(p->inner_iters));
   if (rc != PI_OK) return rc;
   rc = finish(L, stream, p->d_state, p->h_state, 1);
   if (rc != PI_OK) return rc;
@@ -319,7 +322,7 @@ extern "C" pi_status pi_solve_batched(int64_t count, const pi_plan_t *plans, con
     goto done;
   if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) goto done;
   if (capture(L, cap, inner, bicg, &exec) != hipSuccess) goto done;
-  rc = iterate(exec, stream, L.sts, hst, count, max_iter);
+  rc = iterate(exec, stream, L.sts, hst, count, max_iter, unroll_for(inner));
   if (rc != PI_OK) goto done;
   rc = finish(L, stream, L.sts, hst, count);
   if (rc != PI_OK) goto done;

@@ -327,3 +327,33 @@ def test_derived_codes_and_lane_widths_match_stored_codes(ndim, dims):
     assert torch.equal(a.P.cpu(), b.P.cpu())
     gen.close()
     stored.close()
+
+
+FP_CASES = [fp64_cases()[0], fp64_cases()[2], fp64_cases()[4], fp32_cases()[1], fp32_cases()[3]]
+
+
+@pytest.mark.parametrize("name,make", FP_CASES, ids=[c[0] for c in FP_CASES])
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_fixed_point_cg_variant_reaches_the_same_field(name, make, fp64):
+    """The PI_FIXED_POINT_CG variant solves the fixed point of Eq.
+    MatrixEquation directly; its converged field must meet the same bars
+    against the oracle's fixed point, in far fewer inner iterations."""
+    import paper_2311_16935_amd as pi
+
+    announce("fixed-point cg", name, fp64)
+    w = make()
+    sys_ = oracle_for(w)
+    g = _grads(w, fp64)
+    plan = pi.Plan(w.dims, w.spacing, mask=w.mask, fp64=fp64, fixed_point=True)
+    res = plan.solve(g, tol=1e-13 if fp64 else 1e-10, max_iter=2000)
+    assert res.status == 0, res.info
+    P = np_(res.P).astype(np.float64)
+    assert np.all(np.isnan(P[~sys_.valid]))
+    ref = fixed_point(sys_, sys_.source([np_(x).astype(np.float64) for x in g]))
+    err = rel_maxabs(P[sys_.valid], ref)
+    assert err <= (1e-11 if fp64 else 1e-5), err
+    # the paper's iteration needs many more passes for the same tolerance
+    base = _plan(w, fp64).solve(g, tol=1e-6, max_iter=300000)
+    fast = plan.solve(g, tol=1e-6, max_iter=2000)
+    assert fast.info["inner_iters_total"] < base.info["inner_iters_total"]
+    plan.close()
