@@ -53,8 +53,16 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--kernel-reps", type=int, default=20)
-    ap.add_argument("--mode", choices=("solve", "kernels"), default="solve",
-                    help="kernels: only time the outer-step kernels and a copy of known size (for counters)")
+    ap.add_argument("--mode", choices=("solve", "kernels", "batched"), default="solve",
+                    help="kernels: only time the outer-step kernels and a copy of known size (for counters); "
+                         "batched: the uneven batch of 2-D snapshots and 3-D volumes in one batched solve")
+    ap.add_argument("--count2d", type=int, default=512, help="batched mode: 2-D instances")
+    ap.add_argument("--count3d", type=int, default=16, help="batched mode: 3-D instances")
+    ap.add_argument("--fixed-point", action="store_true", help="batched mode: use the fixed-point CG variant")
+    ap.add_argument("--chunk-outer", type=int, default=4000,
+                    help="batched mode: outer steps per batched call (unfinished instances continue from P)")
+    ap.add_argument("--sequential-sample", type=int, default=8,
+                    help="batched mode: instances also solved one by one, to compare")
     ap.add_argument("--no-autotune", action="store_true", help="keep the size-based default tile")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2311_16935_amd", "weights",
                                                       "unet_blobs64.safetensors"),
@@ -236,12 +244,89 @@ def variant_leg(args, pi, grads, P_plain, n, spacing, weights_ok):
     return out
 
 
+def batched_mode(args):
+    """Uneven batch (2-D Lamb-Oseen snapshots with sides U{128..1024} and
+    0-5 % disk masks, 3-D blob volumes with sides U{64..256}, 5 % noise, seeds
+    4000 + i) in batched calls of at most --chunk-outer outer steps each;
+    instances that are not done continue from their returned P."""
+    import torch
+
+    import paper_2311_16935_amd as pi
+    import synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    works = synth.batched_instances(args.count2d, args.count3d, device=dev)
+    progress(f"{len(works)} instances generated ({time.perf_counter() - t0:.1f} s)")
+    grads, plans = [], []
+    for i, w in enumerate(works):
+        grads.append([g.float().contiguous() for g in w.grads])
+        mask = None if w.mask is None else w.mask.cpu()
+        plans.append(pi.Plan(w.dims, w.spacing, mask=mask, fixed_point=args.fixed_point))
+        if args.no_autotune is False:
+            plans[-1].autotune(reps=3)
+        if (i + 1) % 64 == 0 or i + 1 == len(works):
+            progress(f"planned {i + 1}/{len(works)} ({time.perf_counter() - t0:.1f} s)")
+    cells = sum(w.ncells for w in works)
+    Ps = [torch.zeros(p.shape, dtype=torch.float32, device=dev) for p in plans]
+    todo = list(range(len(works)))
+    outer = [0] * len(works)
+    inner = [0] * len(works)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    first = True
+    while todo:
+        rc, _, infos = pi.solve_batched([plans[i] for i in todo], [grads[i] for i in todo], [Ps[i] for i in todo],
+                                        tol=args.tol, max_iter=args.chunk_outer, warm_start=not first, check=False)
+        first = False
+        left = []
+        for i, info in zip(todo, infos):
+            outer[i] += info["outer_iters"]
+            inner[i] += info["inner_iters_total"]
+            if info["status"] == pi.PI_ERR_NOT_CONVERGED:
+                left.append(i)
+            elif info["status"] != pi.PI_OK:
+                raise pi.PiError(info["status"], f"instance {i}")
+        todo = left
+        progress(f"batched call: {len(works) - len(todo)}/{len(works)} done, {time.perf_counter() - t1:.1f} s")
+    torch.cuda.synchronize()
+    batch_s = time.perf_counter() - t1
+    # a few instances alone, for the batched-against-sequential comparison
+    rng = __import__("random").Random(0)
+    sample = sorted(rng.sample(range(len(works)), min(args.sequential_sample, len(works))))
+    seq_s = 0.0
+    for i in sample:
+        P = torch.zeros(plans[i].shape, dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        r = plans[i].solve(grads[i], P=P, tol=args.tol)
+        torch.cuda.synchronize()
+        seq_s += time.perf_counter() - a
+    progress(f"{len(sample)} instances one by one: {seq_s:.1f} s")
+    out = {
+        "metric": "time-to-residual per uneven batch" + (" (fixed-point CG variant)" if args.fixed_point else ""),
+        "value": batch_s, "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
+        "reductions_dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batched_{args.count2d}x2d_{args.count3d}x3d", "count2d": args.count2d,
+                   "count3d": args.count3d, "cells": cells, "tol_eps_R": args.tol, "seeds": "4000+i",
+                   "chunk_outer": args.chunk_outer, "autotuned": not args.no_autotune},
+        "outer_iters": {"max": max(outer), "mean": sum(outer) / len(outer)},
+        "inner_iters_total": sum(inner),
+        "sequential_sample": {"instances": sample, "seconds": seq_s,
+                              "estimated_all_one_by_one": seq_s * len(works) / max(1, len(sample))},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the solver has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batched":
+        batched_mode(args)
+        return
     import torch
 
     import paper_2311_16935_amd as pi
