@@ -7,7 +7,8 @@
 // The marching lane keeps the values of the previous and the next plane in
 // registers, so the stencil reads each vector from HBM about once;
 // x-neighbours come from the lane itself and adjacent lanes, y-neighbours in
-// 3-D from L1/L2.  A block is four strips.  Point-wise kernels instead give
+// 3-D from L1/L2.  A block is four strips, consecutive in memory (x fastest,
+// then y).  Point-wise kernels instead give
 // block b of an instance a contiguous range of cells.  Every kernel of the
 // solve walks a block table whose entries name (instance,
 // block-within-instance), so one launch serves one grid or a whole batch of

@@ -127,21 +127,12 @@ __device__ inline Walk make_walk(const Inst &in, int lb) {
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t)lb * kWavesPerBlock + wave;
   if (w >= in.nwaves) return k;
-  int64_t xs, row, seg;
-  if (in.ndim == 3) {
-    // a block is four consecutive rows of one x strip
-    const int64_t nrg = (in.rows + 3) >> 2;
-    const int64_t rg = w >> 2;
-    xs = rg % in.nxs;
-    const int64_t t = rg / in.nxs;
-    row = (t % nrg) * 4 + (w & 3);
-    seg = t / nrg;
-    if (row >= in.rows) return k;
-  } else {
-    xs = w % in.nxs;
-    seg = w / in.nxs;
-    row = 0;
-  }
+  // strips are numbered x fastest, then y (3-D), then segment, so the four
+  // waves of a block cover consecutive memory of one plane
+  const int64_t xs = w % in.nxs;
+  const int64_t t = w / in.nxs;
+  const int64_t row = in.ndim == 3 ? t % in.rows : 0;
+  const int64_t seg = in.ndim == 3 ? t / in.rows : t;
   k.x = (int)(xs * kWave * W + lane * W);
   k.m0 = (int)(seg * in.mseg);
   k.m1 = min(k.m0 + in.mseg, in.nm);

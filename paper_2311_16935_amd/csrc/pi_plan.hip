@@ -259,7 +259,7 @@ void set_walk(Inst &in, int ndim, const int64_t dims[3], int mseg_override, int 
     in.nm = in.nz;
     in.sm = (int64_t)in.nx * in.ny;
     in.srow = in.nx;
-    strips = (int64_t)in.nxs * ((in.rows + 3) / 4) * 4;
+    strips = (int64_t)in.nxs * in.rows;
   } else {
     in.rows = 1;
     in.nm = in.ny;
