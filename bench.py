@@ -65,7 +65,7 @@ def parse():
                     help="batched mode: instances also solved one by one, to compare")
     ap.add_argument("--no-autotune", action="store_true", help="keep the size-based default tile")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2311_16935_amd", "weights",
-                                                      "unet_blobs64.safetensors"),
+                                                      "unet_blobs128.safetensors"),
                     help="trained warm-start network; the warm-started solve is skipped if missing")
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--no-variant", action="store_true",

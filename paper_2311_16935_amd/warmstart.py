@@ -328,10 +328,13 @@ class WarmStart:
 
 
 # ------------------------------------------------------------------- training
-def make_dataset(n, count, seed_base, tol=1e-6, chunk=32, device="cuda:0", noise=0.05, log=None):
+def make_dataset(n, count, seed_base, tol=1e-6, chunk=32, device="cuda:0", noise=0.05, log=None,
+                 fixed_point=False):
     """Method-generated training pairs on n^3 unit-cube grids of Gaussian-blob
     fields: network input (gradient / RMS, data fraction) and target (the
-    solver's gauge-fixed pressure / (RMS * cell size))."""
+    solver's gauge-fixed pressure / (RMS * cell size)).  fixed_point: solve
+    with the PI_FIXED_POINT_CG variant, which reaches the same fixed point of
+    Eq. MatrixEquation in a fraction of the time."""
     import synth
 
     x = torch.zeros((count, n, n, n, 4), dtype=BF16, device=device)
@@ -346,7 +349,7 @@ def make_dataset(n, count, seed_base, tol=1e-6, chunk=32, device="cuda:0", noise
         works = [synth.config_blobs_3d(n, noise=noise, seed=seed_base + i, device=device) for i in ids]
         grads = [[g.float().contiguous() for g in w.grads] for w in works]
         while len(pool) < len(ids):
-            pool.append(Plan(works[0].dims, works[0].spacing))
+            pool.append(Plan(works[0].dims, works[0].spacing, fixed_point=fixed_point))
         rc, Ps, infos = solve_batched(pool[:len(ids)], grads, tol=tol, max_iter=200000)
         for k, i in enumerate(ids):
             g = grads[k]
