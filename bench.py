@@ -47,6 +47,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="grid side (256 is the benchmark workload)")
+    ap.add_argument("--workload", choices=("blobs3d", "lamb2d"), default="blobs3d",
+                    help="blobs3d: n^3 Gaussian blobs, 5 %% noise; lamb2d: n^2 Lamb-Oseen pair, 10 %% noise, "
+                         "5 %% of cells masked as disks (use --n 2048)")
+    ap.add_argument("--chunk-outer-solve", type=int, default=0,
+                    help="run each timed solve as calls of at most this many outer steps, continuing from P "
+                         "(for solves longer than a few minutes; 0 = one call)")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--seed", type=int, default=9001, help="held out from warm-start training seeds")
     ap.add_argument("--inner", type=int, default=None, help="inner CG iterations per outer step")
@@ -101,13 +107,13 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(n_sample, seed, n_target, tol):
-    """Oracle route O1 on an n_sample^3 grid of the same recipe, timed on this
-    host, scaled to n_target^3: cost per outer step grows with the cell count
-    and the outer-step count with the side length (about 14 n here), so the
-    scale factor is (n_target / n_sample)^4.  The sparse LU's fill grows
-    faster than the cell count in 3-D, so the scaled figure understates the
-    oracle's real cost at 256^3."""
+def cpu_baseline(n_sample, seed, n_target, tol, workload="blobs3d"):
+    """Oracle route O1 on a small grid of the same recipe, timed on this host,
+    scaled to the benchmark grid: cost per outer step grows with the cell
+    count and the outer-step count with the side length, so the scale factor
+    is (n_target / n_sample)^(ndim + 1).  The sparse LU's fill grows faster
+    than the cell count in 3-D, so the scaled figure understates the oracle's
+    real cost at full size."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -115,25 +121,57 @@ def cpu_baseline(n_sample, seed, n_target, tol):
     from oracle.solve import outer_iteration
     from oracle.system import assemble
 
-    w = synth.config_blobs_3d(n_sample, seed=seed)
-    g = [x.float().double().numpy() for x in w.grads]
+    if workload == "lamb2d":
+        w = synth.config_lamb_oseen_2d(n_sample, seed=seed)
+        ndim, what = 2, "Lamb-Oseen pair, masked"
+        mask = np.ones((n_sample,) * 2, np.uint8) if w.mask is None else w.mask.numpy()
+    else:
+        w = synth.config_blobs_3d(n_sample, seed=seed)
+        ndim, what = 3, "blobs"
+        mask = np.ones((n_sample,) * 3, np.uint8)
+    g = [np.nan_to_num(x.float().double().numpy()) for x in w.grads]
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        s = assemble(np.ones((n_sample,) * 3, np.uint8), w.spacing)
+        s = assemble(mask, w.spacing)
         r = outer_iteration(s, s.source(g), tol, 100000)
         t = time.perf_counter() - t0
-    scale = (n_target / n_sample) ** 4
+    scale = (n_target / n_sample) ** (ndim + 1)
     return {
         "value": t * scale,
-        "unit": "s per %d^3 solve to eps_R<=%g (scaled)" % (n_target, tol),
+        "unit": "s per %d^%d solve to eps_R<=%g (scaled)" % (n_target, ndim, tol),
         "cores": 1,
         "kind": "oracle",
-        "sample": f"route O1 (exact sparse-LU inner solve) on {n_sample}^3 blobs, seed {seed}: "
+        "sample": f"route O1 (exact sparse-LU inner solve) on {n_sample}^{ndim} {what}, seed {seed}: "
                   f"{r.outer} outer steps in {t:.2f} s on 1 thread "
-                  f"(host affinity {len(os.sched_getaffinity(0))} cores); scaled by (n/{n_sample})^4",
+                  f"(host affinity {len(os.sched_getaffinity(0))} cores); scaled by (n/{n_sample})^{ndim + 1}",
         "sample_seconds": t,
         "sample_outer_iters": r.outer,
     }
+
+
+def timed_solve(plan, grads, P, tol, chunk, max_iter=10**7):
+    """One solve from P^0 = 0; with chunk > 0 as calls of at most `chunk`
+    outer steps, each continuing from the P the previous one returned."""
+    import paper_2311_16935_amd as pi
+
+    if chunk <= 0:
+        r = plan.solve(grads, P=P, tol=tol, max_iter=max_iter)
+        return r.info
+    P.zero_()
+    outer = inner = 0
+    first = True
+    while True:
+        r = plan.solve(grads, P=P, tol=tol, max_iter=chunk, warm_start=not first, check=False)
+        first = False
+        outer += r.info["outer_iters"]
+        inner += r.info["inner_iters_total"]
+        progress(f"  ... {outer} outer steps, eps_R {r.info['eps_R']:.2e}")
+        if r.status != pi.PI_ERR_NOT_CONVERGED:
+            if r.status != pi.PI_OK:
+                raise pi.PiError(r.status, "pi_solve")
+            info = dict(r.info)
+            info.update(outer_iters=outer, inner_iters_total=inner)
+            return info
 
 
 def kernel_mode(args, pi, plan, grads, P, ncell):
@@ -201,18 +239,21 @@ def warm_start_leg(args, pi, plan, grads, P_plain, n):
             "maxabs_vs_plain_rel_rms": diff}
 
 
-def variant_leg(args, pi, grads, P_plain, n, spacing, weights_ok):
+def variant_leg(args, pi, grads, P_plain, dims, mask, spacing, weights_ok):
     """The PI_FIXED_POINT_CG variant -- CG on the fixed point's operator
     instead of the paper's lagged boundary iteration, same stopping test and
     converged field -- from zero and from the learned guess."""
     import torch
 
-    plan = pi.Plan((n, n, n), spacing, fixed_point=True)
+    plan = pi.Plan(dims, spacing, mask=mask, fixed_point=True)
     plan.autotune(reps=5)
+    n = dims[0]
     P = torch.empty_like(P_plain)
     out = {"inner_per_outer": None}
     for i in range(args.warmup):
         r = plan.solve(grads, P=P, tol=args.tol)
+    rms = float(P_plain.double().pow(2).mean().sqrt()) if mask is None else \
+        float(P_plain.double()[~P_plain.isnan()].pow(2).mean().sqrt())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -221,10 +262,10 @@ def variant_leg(args, pi, grads, P_plain, n, spacing, weights_ok):
     sec = (time.perf_counter() - t0) / max(1, args.steps)
     info = r.info
     assert info["status"] == 0 and info["eps_R"] <= args.tol, info
-    rms = float(P_plain.double().pow(2).mean().sqrt())
+    diff = (P.double() - P_plain.double()).nan_to_num(0.0).abs().max()
     out.update({"s_per_solve": sec, "outer_iters": info["outer_iters"], "inner_iters": info["inner_iters_total"],
                 "eps_R": info["eps_R"], "inner_per_outer": info["inner_iters_total"] // max(1, info["outer_iters"]),
-                "maxabs_vs_plain_rel_rms": float((P.double() - P_plain.double()).abs().max()) / rms})
+                "maxabs_vs_plain_rel_rms": float(diff) / rms})
     progress(f"fixed-point CG variant: {sec:.3f} s per solve, {info['inner_iters_total']} CG iterations")
     if weights_ok:
         from paper_2311_16935_amd.warmstart import UNet, WarmStart
@@ -334,13 +375,29 @@ def main():
 
     dev = torch.device("cuda:0")
     n = args.n
-    w = synth.config_blobs_3d(n, seed=args.seed, device=dev, with_pressure=False)
+    if args.workload == "lamb2d":
+        w = synth.config_lamb_oseen_2d(n, device=dev)
+        dims = (n, n)
+        workload = f"lamb_oseen2d_{n}^2_masked"
+    else:
+        w = synth.config_blobs_3d(n, seed=args.seed, device=dev, with_pressure=False)
+        dims = (n, n, n)
+        workload = f"blobs3d_{n}^3"
+    mask = None if w.mask is None else w.mask.cpu()
     grads = [g.to(torch.float32).contiguous() for g in w.grads]
     del w.grads[:]
-    plan = pi.Plan((n, n, n), w.spacing, fp64=False, inner_iters=args.inner)
-    P = torch.empty((n, n, n), dtype=torch.float32, device=dev)
-    ncell = n ** 3
-    progress(f"plan ready: {n}^3, tile {pi.pi_get_tile(plan.handle)}, {plan.workspace_bytes / 2**30:.2f} GiB")
+    plan = pi.Plan(dims, w.spacing, mask=mask, fp64=False, inner_iters=args.inner)
+    P = torch.empty(plan.shape, dtype=torch.float32, device=dev)
+    ncell = 1
+    for v in dims:
+        ncell *= v
+    # a masked grid reads the 4-byte counter code in both stencil kernels
+    bytes_per_cell = dict(BYTES_PER_CELL)
+    if mask is not None:
+        bytes_per_cell["k_outer"] += 4
+        bytes_per_cell["k_cg_spmv"] += 4
+    progress(f"plan ready: {workload}, tile {pi.pi_get_tile(plan.handle)}, "
+             f"{plan.workspace_bytes / 2**30:.2f} GiB, {pi.lib.pi_get_lane_cells(plan.handle)} cells per lane")
     tune = None
     if not args.no_autotune:
         t0 = time.perf_counter()
@@ -351,48 +408,47 @@ def main():
         kernel_mode(args, pi, plan, grads, P, ncell)
         return
     for i in range(args.warmup):
-        r = plan.solve(grads, P=P, tol=args.tol)
-        progress(f"warmup {i}: {r.info['ms'] / 1e3:.2f} s, {r.info['outer_iters']} outer steps")
+        info = timed_solve(plan, grads, P, args.tol, args.chunk_outer_solve)
+        progress(f"warmup {i}: {info['outer_iters']} outer steps")
     torch.cuda.synchronize()
-    infos = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        r = plan.solve(grads, P=P, tol=args.tol)
-        infos.append(r.info)
-        progress(f"step {i}: {r.info['ms'] / 1e3:.2f} s")
+        info = timed_solve(plan, grads, P, args.tol, args.chunk_outer_solve)
+        progress(f"step {i}: {info['outer_iters']} outer steps, {time.perf_counter() - t0:.2f} s so far")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     sec = elapsed / max(1, args.steps)
-    info = infos[-1]
     assert info["status"] == 0 and info["eps_R"] <= args.tol, info
     P_plain = P.clone()
     warm = None
-    weights_ok = not args.no_warm and os.path.exists(args.weights)
+    weights_ok = not args.no_warm and os.path.exists(args.weights) and len(dims) == 3
     if weights_ok:
         warm = warm_start_leg(args, pi, plan, grads, P_plain, n)
     variant = None
     if not args.no_variant:
-        variant = variant_leg(args, pi, grads, P_plain, n, w.spacing, weights_ok)
+        variant = variant_leg(args, pi, grads, P_plain, dims, mask, w.spacing, weights_ok)
 
     # kernel durations, measured with HIP events on the library's stream
     src_hash = kernel_source_hash()
     kern = {}
     for name, kid in (("k_outer", pi.PI_K_OUTER), ("k_cg_spmv", pi.PI_K_SPMV), ("k_cg_update", pi.PI_K_UPDATE)):
         ms = pi.pi_time_kernel(plan.handle, kid, args.kernel_reps)
-        alg = BYTES_PER_CELL[name] * ncell
+        alg = bytes_per_cell[name] * ncell
         kern[name] = {"avg_ms": ms, "alg_bytes": alg, "achieved_GBs": alg / (ms * 1e-3) / 1e9}
+    # the last CG iteration of every outer step has no update launch (folded into the outer kernel)
     launches = {"k_outer": info["outer_iters"] + 1, "k_cg_spmv": info["inner_iters_total"],
-                "k_cg_update": info["inner_iters_total"]}
+                "k_cg_update": info["inner_iters_total"] - info["outer_iters"]}
     for name in kern:
         kern[name]["launches_per_solve"] = launches[name]
         kern[name]["share_of_solve"] = launches[name] * kern[name]["avg_ms"] * 1e-3 / sec
     dom = max(kern, key=lambda k: kern[k]["launches_per_solve"] * kern[k]["avg_ms"])
     d = kern[dom]
-    traffic = traffic_from_profile(dom, n, src_hash)
+    traffic = traffic_from_profile(dom, n, src_hash) if args.workload == "blobs3d" else None
     roof = {"kernel": dom, "bound": "hbm", "achieved": d["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": d["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
-            "bytes_per_cell": BYTES_PER_CELL[dom], "cells_per_launch": ncell}
-
+            "bytes_per_cell": bytes_per_cell[dom], "cells_per_launch": ncell}
+    recipe = ({"nblobs": 32, "noise": 0.05, "seed": args.seed} if args.workload == "blobs3d" else
+              {"vortices": 2, "core_radius": 0.05, "noise": 0.10, "masked_fraction": 0.05, "seed": 2})
     out = {
         "metric": "time-to-residual 1e-6 per 256^3 solve, plain vs learned warm start; HBM GB/s",
         "value": sec,
@@ -407,10 +463,10 @@ def main():
         "dtype": "f32",
         "reductions_dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"blobs3d_{n}^3", "n": n, "cells": ncell, "nblobs": 32, "noise": 0.05,
-                   "seed": args.seed, "tol_eps_R": args.tol, "start": "P0=0 (plain)",
-                   "inner_cg_iters": info["inner_iters_total"] // max(1, info["outer_iters"]),
-                   "parallelism": "single GPU"},
+        "config": dict({"workload": workload, "n": n, "cells": ncell}, **recipe,
+                       tol_eps_R=args.tol, start="P0=0 (plain)",
+                       inner_cg_iters=info["inner_iters_total"] // max(1, info["outer_iters"]),
+                       parallelism="single GPU"),
         "solve": {"outer_iters": info["outer_iters"], "inner_iters": info["inner_iters_total"],
                   "eps_R": info["eps_R"], "eps_P": info["eps_P"],
                   "outer_point_iters_per_s": ncell * info["outer_iters"] / sec,
@@ -426,7 +482,8 @@ def main():
     del grads, P
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, args.seed, n, args.tol)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n if args.workload == "blobs3d" else 96, args.seed, n,
+                                           args.tol, args.workload)
     print(json.dumps(out), flush=True)
 
 
