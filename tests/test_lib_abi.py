@@ -9,9 +9,9 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = ["include/pi.h", "include/pi_unet.h"]
-LIBS = {"include/pi.h": "paper_2311_16935_amd/libpi.so", "include/pi_unet.h": "paper_2311_16935_amd/libpi.so"}
-PREFIX = {"include/pi.h": "pi", "include/pi_unet.h": "pu"}
+HEADERS = ["include/pi.h", "include/pi_unet.h", "include/pi_flow.h"]
+LIBS = {h: "paper_2311_16935_amd/libpi.so" for h in HEADERS}
+PREFIX = {"include/pi.h": "pi", "include/pi_unet.h": "pu", "include/pi_flow.h": "pi"}
 
 
 def declared(header):
@@ -27,7 +27,7 @@ def test_library_exports_every_declared_function(header):
     lib_path = os.path.join(ROOT, LIBS[header])
     assert os.path.exists(lib_path), "build the library first (__graft_entry__.build())"
     names = declared(header)
-    assert len(names) >= 8
+    assert len(names) >= (1 if header.endswith("pi_flow.h") else 8)
     lib = ctypes.CDLL(lib_path)
     for n in names:
         assert hasattr(lib, n), n
@@ -52,6 +52,15 @@ def test_layer_binding_names_match_header():
     assert sorted(unet.EXPORTED) == names
     for n in names:
         assert callable(getattr(unet, n))
+
+
+def test_flow_binding_names_match_header():
+    from paper_2311_16935_amd import flow
+
+    names = declared("include/pi_flow.h")
+    assert sorted(flow.EXPORTED) == names
+    for n in names:
+        assert callable(getattr(flow, n))
 
 
 def test_status_strings_without_gpu():
