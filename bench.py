@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--kernel-reps", type=int, default=20)
-    ap.add_argument("--mode", choices=("solve", "kernels", "batched"), default="solve",
+    ap.add_argument("--mode", choices=("solve", "kernels", "batched", "flow"), default="solve",
                     help="kernels: only time the outer-step kernels and a copy of known size (for counters); "
                          "batched: the uneven batch of 2-D snapshots and 3-D volumes in one batched solve")
     ap.add_argument("--count2d", type=int, default=512, help="batched mode: 2-D instances")
@@ -74,6 +74,8 @@ def parse():
                                                       "unet_blobs128.safetensors"),
                     help="trained warm-start network; the warm-started solve is skipped if missing")
     ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--no-pressure", action="store_true",
+                    help="flow mode: report the source kernel only, without integrating the pressure")
     ap.add_argument("--no-variant", action="store_true",
                     help="skip the fixed-point CG variant (not the paper's iteration), reported beside it")
     return ap.parse_args()
@@ -83,10 +85,10 @@ def progress(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def traffic_from_profile(kernel, n, src_hash):
+def traffic_from_profile(kernel, n, src_hash, workload="blobs"):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_blobs{n}_pmc.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}{n}_pmc.txt")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -97,11 +99,11 @@ def traffic_from_profile(kernel, n, src_hash):
     return float(m_b.group(1))
 
 
-def kernel_source_hash():
+def kernel_source_hash(files=("pi_kernels.hip", "pi_common.h")):
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("pi_kernels.hip", "pi_common.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2311_16935_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -359,6 +361,88 @@ def batched_mode(args):
     print(json.dumps(out), flush=True)
 
 
+FLOW_BYTES_PER_CELL = 9 * 4 + 3 * 4   # u, u(t - dt), u(t + dt) in (3 x 3 FP32); f out (3 FP32)
+
+
+def flow_mode(args):
+    """Velocity -> source -> pressure on an n^3 decaying ABC flow (exact
+    Navier-Stokes solution, P = -rho |u|^2 / 2): the source kernel timed with
+    HIP events on the stream it runs on, against the HBM roofline, then the
+    pressure integrated from it (paper iteration and fixed-point CG variant)
+    and compared with the analytic pressure."""
+    import torch
+
+    import paper_2311_16935_amd as pi
+    import synth
+    from paper_2311_16935_amd import flow
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    rho, nu, t, dt = 1.0, 0.5, 0.2, 1e-3
+    snaps = []
+    for tt in (t, t - dt, t + dt):
+        u, P, sp = synth.abc_velocity((n, n, n), t=tt, nu=nu, rho=rho, device=dev)
+        snaps.append([c.float().contiguous() for c in u])
+        if tt == t:
+            P_true = (P - P.mean()).float()
+        del u, P
+    u, up, un = snaps
+    f = [torch.empty_like(u[0]) for _ in range(3)]
+    stream = torch.cuda.current_stream()
+
+    def run():
+        flow.pi_flow_source(flow.PI_FLOW_NS, u, sp, out=f, u_prev=up, u_next=un, rho=rho, mu=rho * nu, dt=dt,
+                            stream=stream)
+
+    for _ in range(args.warmup + 1):
+        run()
+    stream.synchronize()
+    reps = max(1, args.kernel_reps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        run()
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ncell = n ** 3
+    alg = FLOW_BYTES_PER_CELL * ncell
+    gbs = alg / (ms * 1e-3) / 1e9
+    progress(f"k_flow {n}^3: {ms * 1e3:.1f} us per launch, {gbs:.0f} GB/s")
+    # counter yardstick, as in --mode kernels: reads and writes 4 bytes per element
+    x = torch.randint(0, 1 << 30, (ncell,), dtype=torch.int32, device=dev)
+    torch.bitwise_not(x, out=torch.empty_like(x))
+    del x
+    legs = {}
+    for name, fp in (() if args.no_pressure else (("paper_iteration", False), ("fixed_point_cg_variant", True))):
+        plan = pi.Plan((n, n, n), sp, fixed_point=fp)
+        P = torch.empty(plan.shape, dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        info = timed_solve(plan, f, P, args.tol, args.chunk_outer_solve)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - a
+        err = float(torch.sqrt(torch.mean((P.double() - P_true.double()) ** 2)) / P_true.abs().max())
+        legs[name] = {"seconds": sec, "outer_iters": info["outer_iters"], "inner_iters": info["inner_iters_total"],
+                      "eps_R": info["eps_R"], "rms_err_vs_analytic_over_max": err}
+        progress(f"{name}: {sec:.2f} s, {info['outer_iters']} outer steps, error {err:.2e}")
+        plan.close()
+    out = {
+        "metric": f"velocity->source kernel time per {n}^3 snapshot (Navier-Stokes, unsteady, viscous)",
+        "value": ms, "unit": "ms", "n_gpus": 1, "steps": reps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64 arithmetic, f32 fields",
+        "data": "synthetic",
+        "config": {"workload": f"abc_flow_{n}^3", "n": n, "cells": ncell, "rho": rho, "nu": nu, "t": t, "dt": dt},
+        "roofline": {"kernel": "k_flow", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profile("k_flow", n, kernel_source_hash(("pi_flow.hip",)), "abc"),
+                     "bytes_per_cell": FLOW_BYTES_PER_CELL,
+                     "cells_per_launch": ncell},
+        "pressure_from_source": legs,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -367,6 +451,9 @@ def main():
         sys.exit(2)
     if args.mode == "batched":
         batched_mode(args)
+        return
+    if args.mode == "flow":
+        flow_mode(args)
         return
     import torch
 

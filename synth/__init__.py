@@ -1,8 +1,9 @@
 """Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
 
 This package holds no arithmetic of the integration method itself: it only
-builds analytic pressure fields with their exact gradients, adds seeded
-Gaussian noise, and draws missing-data masks.  Everything returned is a plain
+builds analytic pressure fields with their exact gradients, analytic
+velocity fields with their pressures, adds seeded noise (to gradients, or to
+velocity by the paper's two models), and draws missing-data masks.  Everything returned is a plain
 array; callers decide which solver (the HIP library or the CPU oracle) sees it.
 """
 
@@ -24,4 +25,10 @@ from .configs import (  # noqa: F401
     config_blobs_3d,
     batched_instances,
     random_small,
+)
+from .velocity import (  # noqa: F401
+    taylor_velocity,
+    abc_velocity,
+    noise_angular,
+    noise_multiplicative,
 )
