@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--kernel-reps", type=int, default=20)
-    ap.add_argument("--mode", choices=("solve", "kernels", "batched", "flow"), default="solve",
+    ap.add_argument("--mode", choices=("solve", "kernels", "batched", "flow", "sequence"), default="solve",
                     help="kernels: only time the outer-step kernels and a copy of known size (for counters); "
                          "batched: the uneven batch of 2-D snapshots and 3-D volumes in one batched solve")
     ap.add_argument("--count2d", type=int, default=512, help="batched mode: 2-D instances")
@@ -74,6 +74,7 @@ def parse():
                                                       "unet_blobs128.safetensors"),
                     help="trained warm-start network; the warm-started solve is skipped if missing")
     ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--snapshots", type=int, default=6, help="sequence mode: snapshots of the 3-D sequence")
     ap.add_argument("--no-pressure", action="store_true",
                     help="flow mode: report the source kernel only, without integrating the pressure")
     ap.add_argument("--no-variant", action="store_true",
@@ -443,6 +444,98 @@ def flow_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def sequence_mode(args):
+    """Time-resolved sequences, each snapshot solved from zero and from the
+    previous snapshot's pressure: (1) n^3 drifting blobs (32 blobs, seed
+    --seed, velocities N(0, (1/n)^2) per axis and snapshot, so a blob moves
+    about one cell per snapshot; 5 % gradient noise); (2) the Taylor-vortex
+    series of the 2-D benchmark section (26 snapshots, 0.05 <= t <= 0.3,
+    101^2 on [-3, 3]^2), velocity -> source (pi_flow_source) -> pressure."""
+    import numpy as np
+    import torch
+
+    import paper_2311_16935_amd as pi
+    import synth
+    from paper_2311_16935_amd import flow
+    from paper_2311_16935_amd.sequence import solve_sequence
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    snaps = []
+    for k in range(args.snapshots):
+        _, g, sp = synth.gaussian_blobs((n, n, n), seed=args.seed, device=dev, with_pressure=False, t=float(k),
+                                        speed=1.0 / n)
+        g = synth.add_noise(g, None, 0.05, args.seed + 1000 + k, device=dev)
+        snaps.append([c.float().contiguous() for c in g])
+        del g
+    progress(f"{len(snaps)} snapshots of {n}^3 drifting blobs generated")
+    out_legs = {}
+    for name, fp in (("paper_iteration", False), ("fixed_point_cg_variant", True)):
+        if fp and args.no_variant:
+            continue
+        plan = pi.Plan((n, n, n), sp, fixed_point=fp)
+        if not args.no_autotune:
+            plan.autotune(reps=3)
+        leg = {}
+        for warm in (False, True):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = solve_sequence(plan, snaps, tol=args.tol, warm=warm)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            assert all(r.status == 0 for r in res), [r.info for r in res]
+            leg["warm" if warm else "cold"] = {
+                "seconds_per_snapshot": sec / len(snaps),
+                "outer_iters": [r.info["outer_iters"] for r in res],
+                "inner_iters": [r.info["inner_iters_total"] for r in res]}
+            if warm:
+                leg["max_diff_warm_vs_cold_over_rms"] = max(
+                    float((a.P - b.P).abs().max() / b.P.pow(2).mean().sqrt()) for a, b in zip(res, cold))
+            else:
+                cold = res
+            progress(f"{name} {'warm' if warm else 'cold'}: {sec / len(snaps):.3f} s per snapshot, outer "
+                     f"{leg['warm' if warm else 'cold']['outer_iters']}")
+        del cold
+        plan.close()
+        out_legs[name] = leg
+    # the paper's 2-D Taylor-vortex series, from velocity
+    m, dtv = 101, 1e-4
+    srcs = []
+    for t in np.linspace(0.05, 0.3, 26):
+        u, _, sp2 = synth.taylor_velocity((m, m), t=t, device=dev)
+        up = synth.taylor_velocity((m, m), t=t - dtv, device=dev)[0]
+        un = synth.taylor_velocity((m, m), t=t + dtv, device=dev)[0]
+        f32 = [[c.float().contiguous() for c in v] for v in (u, up, un)]
+        srcs.append(flow.pi_flow_source(flow.PI_FLOW_NS, f32[0], sp2, u_prev=f32[1], u_next=f32[2], rho=1.0,
+                                        mu=1.0, dt=dtv))
+    plan = pi.Plan((m, m), sp2)
+    tv = {}
+    for warm in (False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = solve_sequence(plan, srcs, tol=args.tol, warm=warm)
+        torch.cuda.synchronize()
+        tv["warm" if warm else "cold"] = {"seconds_total": time.perf_counter() - t0,
+                                          "outer_iters_total": sum(r.info["outer_iters"] for r in res)}
+    plan.close()
+    progress(f"taylor vortex series: cold {tv['cold']}, warm {tv['warm']}")
+    w, c = out_legs["paper_iteration"]["warm"], out_legs["paper_iteration"]["cold"]
+    out = {
+        "metric": f"time-to-residual {args.tol:g} per {n}^3 snapshot of a time-resolved sequence, warm-started "
+                  "from the previous snapshot",
+        "value": w["seconds_per_snapshot"], "unit": "s", "n_gpus": 1, "steps": args.snapshots, "warmup": 0,
+        "ms_per_step": w["seconds_per_snapshot"] * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "reductions_dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"drifting_blobs3d_{n}^3_x{args.snapshots}", "n": n, "snapshots": args.snapshots,
+                   "nblobs": 32, "blob_speed_per_snapshot": 1.0 / n, "noise": 0.05, "seed": args.seed,
+                   "tol_eps_R": args.tol},
+        "cold_seconds_per_snapshot": c["seconds_per_snapshot"],
+        "legs": out_legs,
+        "taylor_vortex_series_101": tv,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -454,6 +547,9 @@ def main():
         return
     if args.mode == "flow":
         flow_mode(args)
+        return
+    if args.mode == "sequence":
+        sequence_mode(args)
         return
     import torch
 

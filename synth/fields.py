@@ -147,14 +147,18 @@ def lamb_oseen_pair(shape, seed, rc=0.05, device="cpu", dtype=torch.float64, wit
 
 
 def gaussian_blobs(shape, seed, nblobs=32, sigma_range=(0.02, 0.1), device="cpu",
-                   dtype=torch.float64, with_pressure=True):
+                   dtype=torch.float64, with_pressure=True, t=0.0, speed=0.0):
     """P = sum_k a_k exp(-|x - c_k|^2 / (2 sigma_k^2)) on the unit square/cube,
-    c_k ~ U[0,1]^d, sigma_k ~ U[sigma_range], a_k ~ N(0, 1)."""
+    c_k ~ U[0,1]^d, sigma_k ~ U[sigma_range], a_k ~ N(0, 1).  With speed > 0
+    the blobs drift: c_k(t) = c_k + t v_k, v_k ~ N(0, speed^2) per axis (drawn
+    after the other parameters, so t = 0 gives the static field of the seed)."""
     nd = len(shape)
     rng = np.random.default_rng(seed)
     cs = rng.uniform(0.0, 1.0, size=(nblobs, nd))
     sig = rng.uniform(sigma_range[0], sigma_range[1], size=nblobs)
     amp = rng.normal(size=nblobs)
+    if speed > 0.0:
+        cs = cs + t * rng.normal(0.0, speed, size=(nblobs, nd))
     X, spacing = cell_centers(shape, device=device, dtype=dtype)
     s = tuple(reversed([int(n) for n in shape]))
     P = torch.zeros(s, device=device, dtype=dtype) if with_pressure else None
