@@ -19,8 +19,12 @@ system     explicit sparse assembly of [W^{n+1}], [W^n] and {S}
 solve      Algorithm 1 with an exact sparse-LU inner solve (route O1), the
            direct solve of its fixed point (route O2), the residuals of Eqs.
            ResidualPressure / ResidualMomentum, and the per-component gauge.
-rays       brute-force ray tracing: counters from explicit rays, and a
-           rotating-parallel-ray omnidirectional integrator on tiny grids.
+rays       brute-force ray tracing: counters from explicit rays (face-crossing
+           and cell-centred paths), and a rotating-parallel-ray
+           omnidirectional integrator on tiny grids.
+cellcentered  the 2-D cell-centred scheme: counters by tracing the
+           nearest-centre paths over all angles and offsets, and its system.
+flow       the velocity -> source stage (Navier-Stokes, RANS, compressible).
 unet       FP64 reference of the warm-start network's layers (forward and
            backward), written as plain direct convolutions.
 

@@ -251,3 +251,76 @@ def omni_rays_2d(mask, spacing, grads, n_angles=720, ds_frac=0.05, tol=1e-13, ma
     out = np.full(mask.shape, np.nan)
     out[valid] = P
     return out, sweeps
+
+
+def cc_counters_bruteforce(mask, spacing, n_theta=1440, ds=0.01):
+    """Cell-centred counters from explicit rays (2-D): midpoint rules in the
+    angle and the perpendicular offset; every ray is a straight line, its
+    path the cells whose centres are nearest to it in each column (a ray
+    less steep than the diagonal) or each row (a steeper ray).  For every
+    data cell C on a path, the previous cell J and the one before it K
+    decide the counter: J missing -> A_C^n, K missing -> A_J^n, else
+    A_J^{n+1}.  Cells outside the grid count as missing.  Returns the same
+    keys as oracle.cellcentered.cc_counters (without 'Atot')."""
+    mask = np.asarray(mask) != 0
+    ny, nx = mask.shape
+    hx, hy = (float(s) for s in spacing)
+    names = {(1, 0): "E", (-1, 0): "W", (0, 1): "N", (0, -1): "S",
+             (1, 1): "NE", (-1, 1): "NW", (1, -1): "SE", (-1, -1): "SW"}
+    out = {(n, i): np.zeros((ny, nx)) for n in names.values() for i in ("np1", "n")}
+    out["C_n"] = np.zeros((ny, nx))
+    ext = 3
+    ox, oy = 0.5 * nx * hx, 0.5 * ny * hy
+    R = math.hypot(ox, oy) + 3 * max(hx, hy)
+    s = np.arange(-R + 0.5 * ds, R, ds)
+    dth = 2 * math.pi / n_theta
+
+    def data(i, j):
+        inside = (i >= 0) & (i < nx) & (j >= 0) & (j < ny)
+        v = np.zeros(i.shape, dtype=bool)
+        v[inside] = mask[j[inside], i[inside]]
+        return v, inside
+
+    for t in range(n_theta):
+        th = (t + 0.5) * dth
+        cx, cy = math.cos(th), math.sin(th)
+        px, py = ox - s * cy, oy + s * cx           # a point of each ray
+        if abs(cx) * hy >= abs(cy) * hx:            # shallow: one cell per column
+            cols = np.arange(-ext, nx + ext)
+            if cx < 0:
+                cols = cols[::-1]
+            xc = (cols + 0.5) * hx
+            tt = (xc[None, :] - px[:, None]) / cx
+            yc = py[:, None] + tt * cy
+            I = np.broadcast_to(cols[None, :], yc.shape)
+            Jr = np.floor(yc / hy).astype(np.int64)
+        else:                                       # steep: one cell per row
+            rows = np.arange(-ext, ny + ext)
+            if cy < 0:
+                rows = rows[::-1]
+            yc = (rows + 0.5) * hy
+            tt = (yc[None, :] - py[:, None]) / cy
+            xc2 = px[:, None] + tt * cx
+            Jr = np.broadcast_to(rows[None, :], xc2.shape)
+            I = np.floor(xc2 / hx).astype(np.int64)
+        w = dth * ds
+        for p in range(2, I.shape[1]):
+            ci, cj = I[:, p], Jr[:, p]
+            vc, _ = data(ci, cj)
+            if not vc.any():
+                continue
+            ji, jj = I[:, p - 1], Jr[:, p - 1]
+            ki, kj = I[:, p - 2], Jr[:, p - 2]
+            vj, _ = data(ji, jj)
+            vk, _ = data(ki, kj)
+            for key, sel in (("C_n", vc & ~vj), ("np1", vc & vj & vk), ("n", vc & vj & ~vk)):
+                if not sel.any():
+                    continue
+                if key == "C_n":
+                    np.add.at(out["C_n"], (cj[sel], ci[sel]), w)
+                    continue
+                for (dx, dy), nm in names.items():
+                    sub = sel & (ji - ci == dx) & (jj - cj == dy)
+                    if sub.any():
+                        np.add.at(out[(nm, key)], (cj[sub], ci[sub]), w)
+    return out
