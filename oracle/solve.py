@@ -11,8 +11,9 @@ Route O2 -- the fixed point.  At convergence {P^{n+1}} = {P^n} = P, so
 face total and all counters add up to A_tot (Eq. Atot2D and its 3-D analogue,
 and the remark after the appendix cell-1 example), which makes M - N a
 symmetric, zero-row-sum operator: P is defined up to one constant per
-connected group of valid cells.  O2 solves it with one cell per group pinned,
-then applies the gauge.
+connected group of valid cells.  O2 solves it with one cell per group
+pinned (least squares in the rounding-level inconsistency), then applies the
+gauge.
 
 Gauge: the paper fixes the free constant with one reference point (Sections
 on the PIV and SPIV examples).  Here the mean over every face-connected group
@@ -103,16 +104,31 @@ def outer_iteration(system: System, S, tol: float, max_iter: int, P0=None) -> Ou
 
 
 def fixed_point(system: System, S) -> np.ndarray:
-    """Route O2: solve (M - N) P = S with one pinned cell per group, gauged."""
-    L = system.L
+    """Route O2: (M - N) P = S, gauged.
+
+    The fixed point is defined up to one constant per connected group.  An
+    assembled L = M - N has column sums of ~1e-15 instead of 0, so in
+    floating point the equations are inconsistent at rounding level, and
+    the answer wanted is the least-squares one, whose residual is a
+    constant lam_g over each group.  With one cell per group pinned (sparse
+    LU of the rest), the equations of the other cells are met with S - lam
+    and the pinned cell's equation takes the inconsistency; taking lam_g as
+    the mean residual over the group and solving again moves that residual
+    evenly onto the group (left in one equation, it acts as a point
+    source)."""
+    L = system.L.tocsr()
     k, lab = components(system)
     n = system.n
-    P = np.zeros(n)
-    # pin the first cell of every group
+    S = np.asarray(S, dtype=np.float64)
     _, first = np.unique(lab, return_index=True)
     keep = np.ones(n, dtype=bool)
     keep[first] = False
+    P = np.zeros(n)
     if keep.any():
-        Lk = L[keep][:, keep].tocsc()
-        P[keep] = spla.splu(Lk).solve(np.asarray(S)[keep])
+        lu = spla.splu(L[keep][:, keep].tocsc())
+        cnt = np.bincount(lab, minlength=k)
+        lam = np.zeros(k)
+        for _ in range(3):
+            P[keep] = lu.solve((S - lam[lab])[keep])
+            lam = np.bincount(lab, weights=S - L @ P, minlength=k) / cnt
     return gauge(system, P)
