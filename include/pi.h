@@ -65,6 +65,24 @@ typedef struct pi_plan_s *pi_plan_t;
  * field; far fewer passes over the grid.  CG only (not with BiCGStab).
  */
 #define PI_FIXED_POINT_CG 0x4u
+/*
+ * The cell-centred scheme (Section "Method Concept"), 2-D only: a ray's path
+ * is the cells whose centres lie nearest to it, one per column for rays less
+ * steep than the cell diagonal, one per row otherwise, so a cell takes rays
+ * from its 8 face and diagonal neighbours and the pressure is carried from
+ * centre to centre with the trapezoid rule (Eq. ExplicitEqn_FaceCrossing
+ * with the diagonal directions j).  The weights are the measures of those
+ * rays over all angles and offsets: for an interior cell, with D = |(dx,
+ * dy)| and A_tot = 4 D, 2 (D - dx) from each x neighbour, 2 (D - dy) from
+ * each y neighbour and dx + dy - D from each diagonal one.  At boundaries a
+ * ray starts at the first data cell of its path, as in the face-crossing
+ * scheme: its weight moves to [W^n] when the cell before the neighbour holds
+ * no data, to w_C^n when the neighbour holds none.  The paper gives this
+ * scheme's boundary weights only in supplementary material; these follow
+ * from the same definition.  Connected groups (gauge) count diagonal
+ * neighbours.  Not with PI_INNER_BICGSTAB.
+ */
+#define PI_CELL_CENTERED 0x8u
 
 /* pi_solve flags */
 #define PI_WARM_START 0x1u      /* P holds P^0 on entry (else P^0 = 0)            */
@@ -97,7 +115,8 @@ typedef struct pi_info {
  *   mask     host pointer to nx*ny*nz bytes (copied), or NULL = all cells hold
  *            data.  At least one cell must hold data.
  *   flags    PI_FP32 or PI_FP64, ORed with PI_INNER_CG or PI_INNER_BICGSTAB,
- *            optionally ORed with PI_FIXED_POINT_CG (with PI_INNER_CG only).
+ *            optionally ORed with PI_FIXED_POINT_CG (with PI_INNER_CG only)
+ *            and PI_CELL_CENTERED (ndim == 2, PI_INNER_CG only).
  *   out      receives the plan; set to NULL on failure.
  * Errors: PI_ERR_INVALID_ARG, PI_ERR_OOM, PI_ERR_DEVICE.  Synchronous.
  */

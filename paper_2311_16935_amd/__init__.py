@@ -33,6 +33,7 @@ PI_FP64 = 0x1
 PI_INNER_CG = 0x0
 PI_INNER_BICGSTAB = 0x2
 PI_FIXED_POINT_CG = 0x4
+PI_CELL_CENTERED = 0x8
 PI_WARM_START = 0x1
 PI_OP_M, PI_OP_N, PI_OP_L = 0, 1, 2
 
@@ -223,7 +224,8 @@ class Plan:
     """A planned grid: ``dims`` = (nx, ny[, nz]); tensors are in storage
     order, i.e. shaped (ny, nx) or (nz, ny, nx)."""
 
-    def __init__(self, dims, spacing, mask=None, fp64=False, bicgstab=False, inner_iters=None, fixed_point=False):
+    def __init__(self, dims, spacing, mask=None, fp64=False, bicgstab=False, inner_iters=None, fixed_point=False,
+                 cell_centered=False):
         self.dims = tuple(int(v) for v in dims)
         self.ndim = len(self.dims)
         self.spacing = tuple(float(v) for v in spacing)
@@ -232,6 +234,8 @@ class Plan:
         flags = (PI_FP64 if fp64 else PI_FP32) | (PI_INNER_BICGSTAB if bicgstab else PI_INNER_CG)
         if fixed_point:
             flags |= PI_FIXED_POINT_CG
+        if cell_centered:
+            flags |= PI_CELL_CENTERED
         self.handle = pi_plan(self.ndim, self.dims, self.spacing, mask, flags)
         if inner_iters is not None:
             pi_set_inner_iters(self.handle, inner_iters)

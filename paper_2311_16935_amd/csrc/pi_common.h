@@ -28,12 +28,60 @@ constexpr int kXcd = 8;
 constexpr uint32_t kValidBit = 1u << 31;
 constexpr int kStates = 20;      // per-direction counter states (3-D uses 0..18)
 constexpr int kSegCells = 65536; // gauge segment length (cells)
-constexpr int kShapes = 8;       // stencil launch shapes: (2-D, 3-D) x (1, 4 cells per lane) x (codes read, derived)
+constexpr int kShapes = 9;       // stencil launch shapes: (2-D, 3-D) x (1, 4 cells per lane) x (codes read,
+                                 // derived), and the 2-D cell-centred scheme
+constexpr int kShapeCC = 8;
 
 // Launch shape of an instance: bit 0 = 3-D, bit 1 = four cells per lane,
-// bit 2 = no mask (counter codes derived from cell coordinates).
-__host__ __device__ inline int shape_of(int ndim, int vw, int gen) {
+// bit 2 = no mask (counter codes derived from cell coordinates); the
+// cell-centred scheme has a shape of its own.
+__host__ __device__ inline int shape_of(int ndim, int vw, int gen, int cc) {
+  if (cc) return kShapeCC;
   return (ndim == 3 ? 1 : 0) | (vw == 4 ? 2 : 0) | (gen ? 4 : 0);
+}
+
+// Cell-centred scheme: the 8 neighbours J (E, W, N, S, NE, NW, SE, SW) and
+// the bit of cell C + (dx, dy), |dx|, |dy| <= 2, in the 24-bit ring code of a
+// data cell (bit 31 = data).
+__host__ __device__ constexpr int cc_dir(int dx, int dy) {
+  return dy == 0 ? (dx > 0 ? 0 : 1) : dx == 0 ? (dy > 0 ? 2 : 3) : dy > 0 ? (dx > 0 ? 4 : 5) : (dx > 0 ? 6 : 7);
+}
+__host__ __device__ constexpr int cc_dx(int j) { return (j == 0 || j == 4 || j == 6) ? 1 : (j == 1 || j == 5 || j == 7) ? -1 : 0; }
+__host__ __device__ constexpr int cc_dy(int j) { return (j == 2 || j == 4 || j == 5) ? 1 : (j == 3 || j == 6 || j == 7) ? -1 : 0; }
+__host__ __device__ constexpr int cc_bit(int dx, int dy) {
+  return (dy + 2) * 5 + (dx + 2) < 12 ? (dy + 2) * 5 + (dx + 2) : (dy + 2) * 5 + (dx + 2) - 1;
+}
+constexpr uint32_t kCcRing = (1u << 24) - 1;
+
+// The 32 kinds of ray piece of the cell-centred scheme, in a fixed order.
+// Per major axis (rays less steep than the diagonal travel along x, steeper
+// ones along y), travel sign and sign of the lateral slope, the rays through
+// C fall into four pieces by the lateral offsets of the previous cell J and
+// of the cell K before it (one and two steps back along the major axis):
+//   0: J and K one lateral step back        (measure index 0)
+//   1: J straight back, K one lateral step  (measure index 0)
+//   2: J and K straight back                (measure index 1)
+//   3: J one, K two lateral steps back      (measure index 2)
+// f(J direction, bit of J, bit of K, major axis, measure index) is called
+// for each.  The measures come from integrating the piece lengths, linear in
+// tan(angle), over the angle (the plan's constants).
+template <class F>
+__host__ __device__ inline void cc_pieces(F &&f) {
+#pragma unroll
+  for (int maj = 0; maj < 2; ++maj)
+#pragma unroll
+    for (int si = 0; si < 2; ++si)
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int pc = 0; pc < 4; ++pc) {
+          const int sg = si ? -1 : 1, mu = mi ? -1 : 1;
+          const int jM = -sg, jm = (pc == 0 || pc == 3) ? -mu : 0;
+          const int kM = -2 * sg, km = pc == 2 ? 0 : pc == 3 ? -2 * mu : -mu;
+          const int jx = maj ? jm : jM, jy = maj ? jM : jm;
+          const int kx = maj ? km : kM, ky = maj ? kM : km;
+          f(cc_dir(jx, jy), cc_bit(jx, jy), cc_bit(kx, ky), maj, pc == 3 ? 2 : pc == 2 ? 1 : 0);
+        }
 }
 
 // Per-direction code layout: 3-D 5 bits (state = 1 + n1 + 3 n2 + 9 far for a
@@ -69,11 +117,20 @@ struct Inst {
   int32_t ncomp;    // connected groups of data cells
   int32_t inner_iters; // inner Krylov iterations per outer step
   int32_t inner_op; // operator of the inner solve: 0 [W^{n+1}], 1 [W^{n+1}] - [W^n]
+  double inner_floor; // variant: stop the inner CG once r.r falls below this
+                      // fraction of its value at the start of the inner solve
   double inv_nvalid;// 1 / data cells (gauge of a single group)
   double a[6];      // per-direction face total / A_tot
   double dsig[6];   // signed spacing Delta_j
   double lut_np1[6][kStates];  // w_j^{n+1} by direction and state
   double lut_n[6][kStates];    // w_j^{n}   by direction and state
+  // cell-centred scheme (cc != 0): per-direction ray totals over A_tot,
+  // displacement Delta_J = (dx_J h_x, dy_J h_y), and the measures over A_tot
+  // of the three kinds of ray piece per major axis (see cc_weights)
+  int32_t cc;
+  double cc_a[8];
+  double cc_step[8][2];
+  double cc_m[2][3];
   const uint32_t *code;
   // connected groups (all NULL when ncomp == 1): data cells sorted by group,
   // cut into segments of at most kSegCells cells that never straddle groups
@@ -106,6 +163,7 @@ struct Inst {
 struct State {
   double normS2;
   double rr;        // CG: r.r of the current inner residual
+  double rr0;       // CG: r.r at the start of the inner solve
   double alpha, beta;
   double rho, omega;// BiCGStab
   double epsR, epsP;

@@ -1023,6 +1023,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
       } else {
         st->outer += 1;
         st->rr = s[1];
+        st->rr0 = s[1];
         st->inner = 0;
         st->tail = 0;
         st->first = 1;
@@ -1053,8 +1054,14 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
       st->inner_total += 1;
       // fixed-point variant: the inner residual is the outer residual of
       // P + d, so the inner solve stops once it is well below the tolerance
-      // (the FP64 outer step then confirms it)
-      if (in.inner_op != 0 && s[0] <= 0.25 * in.tol * in.tol * st->normS2) st->inner = in.inner_iters;
+      // (the FP64 outer step then confirms it), or once it is as small as
+      // the vector precision can resolve: beyond that only the residual's
+      // rounding-level constant part is left, which the singular operator
+      // cannot reduce (p.q -> 0 and alpha would blow up); the next outer
+      // step restarts from the FP64 residual
+      if (in.inner_op != 0 &&
+          (s[0] <= 0.25 * in.tol * in.tol * st->normS2 || s[0] <= in.inner_floor * st->rr0))
+        st->inner = in.inner_iters;
       break;
     case K_BICG_P:
       st->alpha = s[0] != 0.0 ? st->rho / s[0] : 0.0;
@@ -1152,13 +1159,233 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Ins
   march<ND, W, GEN, T, int, T>(wk, load, load1, aux, body, store);
 }
 
+
+// ---------------------------------------------------------------------------
+// the 2-D cell-centred scheme: 9-point stencils over contiguous cell ranges
+// ---------------------------------------------------------------------------
+// Each lane takes cells of its block's range; the 8 neighbours come from
+// L1/L2 (the ranges are contiguous, so rows y-1, y, y+1 of a block are read
+// by the same CU).  The ring code of a cell tells which of the 24 cells
+// within two steps hold data.
+
+// offset of neighbour j in cells
+__device__ inline int64_t cc_off(const Inst &in, int j) { return (int64_t)cc_dx(j) + (int64_t)cc_dy(j) * in.nx; }
+
+// w_J^{n+1} (np1) and w_J^n (n) of the 8 neighbours from the ray pieces: a
+// piece counts when J holds data, towards n+1 when K holds data as well
+__device__ inline void cc_weights(const Inst &in, uint32_t cd, double (&np1)[8], double (&n)[8]) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) np1[j] = n[j] = 0.0;
+  cc_pieces([&](int J, int jb, int kb, int maj, int mi) {
+    const double m = in.cc_m[maj][mi];
+    if ((cd >> jb) & 1u) {
+      if ((cd >> kb) & 1u) np1[J] += m;
+      else n[J] += m;
+    }
+  });
+}
+
+__device__ inline bool cc_has(uint32_t cd, int j) { return (cd >> cc_bit(cc_dx(j), cc_dy(j))) & 1u; }
+
+// S_C = - sum_J Delta_J . (w_J^{n+1} + w_J^n) (f(J) + f(C)) / 2 over
+// neighbours J with data (the sum of the two weights is the direction's
+// total a_J), FP64
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_source_cc(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                     double *part) {
+  PI_PROLOGUE
+  int64_t beg, end;
+  linear_range(in, e.lb, beg, end);
+  const T *gx = (const T *)in.g[0], *gy = (const T *)in.g[1];
+  T *S = (T *)in.S;
+  double *S64 = in.S64;
+  const uint32_t *code = in.code;
+  double wx[8], wy[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    wx[j] = -0.5 * in.cc_a[j] * in.cc_step[j][0];
+    wy[j] = -0.5 * in.cc_a[j] * in.cc_step[j][1];
+  }
+  double acc[1] = {0.0};
+  int bad = 0;
+  for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
+    const uint32_t cd = code[c];
+    double s = 0.0;
+    if (cd & kValidBit) {
+      const double fx = (double)gx[c], fy = (double)gy[c];
+      if (!isfinite(fx) || !isfinite(fy)) bad = 1;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (!cc_has(cd, j)) continue;
+        const int64_t q = c + cc_off(in, j);
+        if (cc_dx(j) != 0) s += wx[j] * ((double)gx[q] + fx);
+        if (cc_dy(j) != 0) s += wy[j] * ((double)gy[q] + fy);
+      }
+    }
+    S64[c] = s;
+    if (S) S[c] = (T)s;
+    acc[0] += s * s;
+  }
+  if (bad) atomicOr(&st->nonfinite, 1);
+  publish<1>(in, part, e.lb, acc);
+}
+
+// P' = P + delta (the pending last CG step folded in as in k_outer),
+// r = S - (M - N) P' with (M - N) P' = sum_J a_J (P'_C - P'_J)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                    double *part) {
+  PI_PROLOGUE
+  if (skip_outer(st)) return;
+  int64_t beg, end;
+  linear_range(in, e.lb, beg, end);
+  const int cur = st->Pcur;
+  const double *Pold = in.P[cur];
+  double *Pnew = in.P[cur ^ 1];
+  const T at = st->tail ? (T)st->alpha : T(0);
+  const T *pt = (const T *)in.p[st->pcur];
+  const T *dl = (const T *)in.d;
+  const double *S = in.S64;
+  T *res = (T *)in.res;
+  const uint32_t *code = in.code;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
+    const uint32_t cd = code[c];
+    if (!(cd & kValidBit)) {
+      Pnew[c] = 0.0;
+      res[c] = T(0);
+      continue;
+    }
+    const T dC = dl[c] + at * pt[c];
+    const double vC = Pold[c] + (double)dC;
+    double Lp = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (!cc_has(cd, j)) continue;
+      const int64_t q = c + cc_off(in, j);
+      Lp += in.cc_a[j] * (vC - (Pold[q] + (double)(dl[q] + at * pt[q])));
+    }
+    const double r = S[c] - Lp;
+    const double rt = (double)(T)r;
+    acc[0] += r * r;
+    acc[1] += rt * rt;
+    acc[2] += (double)dC * (double)dC;
+    acc[3] += vC * vC;
+    Pnew[c] = vC;
+    res[c] = (T)r;
+  }
+  publish<4>(in, part, e.lb, acc);
+}
+
+// p <- r + beta p, q <- A p, p.q with A = [W^{n+1}] (or the fixed point's
+// operator for the variant)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_spmv_cc(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                      double *part) {
+  PI_PROLOGUE
+  if (skip_inner(in, st)) return;
+  int64_t beg, end;
+  linear_range(in, e.lb, beg, end);
+  const T beta = (T)st->beta;
+  const int pc = st->pcur;
+  const T *pold = (const T *)in.p[pc];
+  T *pnew = (T *)in.p[pc ^ 1];
+  const T *res = (const T *)in.res;
+  T *q = (T *)in.q;
+  const uint32_t *code = in.code;
+  const bool opL = in.inner_op != 0;
+  T a[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] = (T)in.cc_a[j];
+  double acc[1] = {0.0};
+  for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
+    const uint32_t cd = code[c];
+    if (!(cd & kValidBit)) {
+      pnew[c] = T(0);
+      q[c] = T(0);
+      continue;
+    }
+    const T pC = res[c] + beta * pold[c];
+    T nb[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t o = c + cc_off(in, j);
+      nb[j] = cc_has(cd, j) ? res[o] + beta * pold[o] : T(0);
+    }
+    T s;
+    if (opL) {
+      s = T(0);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (cc_has(cd, j)) s += a[j] * (pC - nb[j]);
+    } else if ((cd & kCcRing) == kCcRing) {
+      s = pC;  // every cell within two steps holds data: w^{n+1} = a
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s -= a[j] * nb[j];
+    } else {
+      double np1[8], wn[8];
+      cc_weights(in, cd, np1, wn);
+      s = pC;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s -= (T)np1[j] * nb[j];
+    }
+    acc[0] += (double)pC * (double)s;
+    pnew[c] = pC;
+    q[c] = s;
+  }
+  publish<1>(in, part, e.lb, acc);
+}
+
+// y = M x, N x or (M - N) x for pi_apply
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_apply_cc(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                    double *part, int op, const T *x, T *y) {
+  PI_PROLOGUE
+  int64_t beg, end;
+  linear_range(in, e.lb, beg, end);
+  const uint32_t *code = in.code;
+  for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
+    const uint32_t cd = code[c];
+    if (!(cd & kValidBit)) {
+      y[c] = T(0);
+      continue;
+    }
+    const T vC = x[c];
+    double np1[8], wn[8];
+    cc_weights(in, cd, np1, wn);
+    T s;
+    if (op == 0) {  // M = I - W^{n+1}
+      s = vC;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (cc_has(cd, j)) s -= (T)np1[j] * x[c + cc_off(in, j)];
+    } else if (op == 1) {  // N = W^n, diagonal w_C^n = 1 - sum of a_J over neighbours with data
+      double wc = 1.0;
+      s = T(0);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (cc_has(cd, j)) {
+          s += (T)wn[j] * x[c + cc_off(in, j)];
+          wc -= in.cc_a[j];
+        }
+      s += (T)wc * vC;
+    } else {  // M - N
+      s = T(0);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (cc_has(cd, j)) s += (T)in.cc_a[j] * (vC - x[c + cc_off(in, j)]);
+    }
+    y[c] = s;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
 #define PI_ARGS tab, insts, sts, part
 
 // stencil kernels come in eight shapes (see shape_of)
-#define PI_MARCH(KERN, ...)                                                               \
+#define PI_MARCH8(KERN, ...)                                                              \
   do {                                                                                    \
     switch (shape) {                                                                      \
       case 0: KERN<T, 2, 1, false><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
@@ -1170,6 +1397,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Ins
       case 6: KERN<T, 2, 4, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;             \
       default: KERN<T, 3, 4, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
     }                                                                                     \
+  } while (0)
+
+// ... and the cell-centred scheme has kernels of its own (KERN_cc)
+#define PI_MARCH(KERN, ...)                                                               \
+  do {                                                                                    \
+    if (shape == kShapeCC) KERN##_cc<T><<<grid, block, 0, s>>>(__VA_ARGS__);              \
+    else PI_MARCH8(KERN, __VA_ARGS__);                                                    \
   } while (0)
 
 template <typename T>
@@ -1184,14 +1418,21 @@ static hipError_t launch_t(KernelId k, int shape, const LaunchArgs &la) {
   switch (k) {
     case K_INIT: k_init<T><<<grid, block, 0, s>>>(PI_ARGS, la.iarg); break;
     case K_SOURCE:
-      if (ndim == 3) k_source<T, 3><<<grid, block, 0, s>>>(PI_ARGS);
+      if (shape == kShapeCC) k_source_cc<T><<<grid, block, 0, s>>>(PI_ARGS);
+      else if (ndim == 3) k_source<T, 3><<<grid, block, 0, s>>>(PI_ARGS);
       else k_source<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
       break;
     case K_OUTER: PI_MARCH(k_outer, PI_ARGS); break;
     case K_CG_SPMV: PI_MARCH(k_cg_spmv, PI_ARGS); break;
     case K_CG_UPDATE: k_cg_update<T><<<grid, block, 0, s>>>(PI_ARGS); break;
-    case K_BICG_P: PI_MARCH(k_bicg_spmv_p, PI_ARGS); break;
-    case K_BICG_S: PI_MARCH(k_bicg_spmv_s, PI_ARGS); break;
+    case K_BICG_P:
+      if (shape == kShapeCC) return hipErrorInvalidValue;  // CG only
+      PI_MARCH8(k_bicg_spmv_p, PI_ARGS);
+      break;
+    case K_BICG_S:
+      if (shape == kShapeCC) return hipErrorInvalidValue;
+      PI_MARCH8(k_bicg_spmv_s, PI_ARGS);
+      break;
     case K_BICG_UPDATE: k_bicg_update<T><<<grid, block, 0, s>>>(PI_ARGS); break;
     case K_COPY_RES: k_copy_res<T><<<grid, block, 0, s>>>(PI_ARGS); break;
     case K_GAUGE_GROUPS: k_gauge_groups<<<grid, block, 0, s>>>(PI_ARGS); break;

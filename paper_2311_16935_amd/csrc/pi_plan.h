@@ -16,6 +16,7 @@ struct pi_plan_s {
   bool fp64 = false;
   bool bicgstab = false;
   bool fixed_point = false;  // PI_FIXED_POINT_CG variant
+  bool cc = false;           // PI_CELL_CENTERED scheme (2-D)
   int inner_iters = 4;
   int64_t ncell = 0;
   int64_t nvalid = 0;

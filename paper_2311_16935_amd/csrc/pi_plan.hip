@@ -78,6 +78,32 @@ hipError_t launch_codes(int ndim, int nx, int ny, int nz, const uint8_t *mask, u
   return hipGetLastError();
 }
 
+// Cell-centred scheme (2-D): bit 31 = data, bit cc_bit(dx, dy) = data at
+// C + (dx, dy) for |dx|, |dy| <= 2; cells outside the grid hold no data.
+__global__ __launch_bounds__(256) void k_codes_cc(int nx, int ny, const uint8_t *mask, uint32_t *code) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t)nx * ny) return;
+  const int x = (int)(c % nx), y = (int)(c / nx);
+  auto valid = [&](int px, int py) -> bool {
+    return px >= 0 && px < nx && py >= 0 && py < ny && mask[(int64_t)px + (int64_t)nx * py] != 0;
+  };
+  if (!valid(x, y)) {
+    code[c] = 0u;
+    return;
+  }
+  uint32_t out = kValidBit;
+  for (int dy = -2; dy <= 2; ++dy)
+    for (int dx = -2; dx <= 2; ++dx)
+      if ((dx != 0 || dy != 0) && valid(x + dx, y + dy)) out |= 1u << cc_bit(dx, dy);
+  code[c] = out;
+}
+
+hipError_t launch_codes_cc(int nx, int ny, const uint8_t *mask, uint32_t *code) {
+  const int64_t nb = ((int64_t)nx * ny + 255) / 256;
+  k_codes_cc<<<dim3((unsigned)nb), dim3(256), 0, nullptr>>>(nx, ny, mask, code);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // quadrature for the anisotropic 3-D constants
 // ---------------------------------------------------------------------------
@@ -242,6 +268,39 @@ static void fill_luts(pi_plan_s *p, Inst &in) {
   }
 }
 
+// Cell-centred constants.  Along major axis spacing hM (lateral hm), a ray
+// at angle phi from the axis, 0 < phi < phi_d = atan(hm / hM), shifts
+// laterally by tau = hM tan(phi) / hm cells per step; the rays through C
+// cover lateral offsets of one cell with measure hm cos(phi) per unit offset
+// and angle.  The four pieces (see cc_pieces) have lengths tau, tau,
+// 1 - 2 tau, 0 for tau < 1/2 and 1 - tau, 1 - tau, 0, 2 tau - 1 above, so
+// with phi_h = atan(hm / (2 hM)) their measures integrate to
+//   m0 = hM (1 - cos phi_h) + hm (sin phi_d - sin phi_h) - hM (cos phi_h - cos phi_d)
+//   m1 = hm sin phi_h - 2 hM (1 - cos phi_h)
+//   m2 = 2 hM (cos phi_h - cos phi_d) - hm (sin phi_d - sin phi_h)
+// All rays through a cell measure A_tot = 4 |(dx, dy)|.
+static void fill_cc(pi_plan_s *p, Inst &in) {
+  const double hx = p->spacing[0], hy = p->spacing[1];
+  const double Atot = 4.0 * sqrt(hx * hx + hy * hy);
+  for (int maj = 0; maj < 2; ++maj) {
+    const double hM = maj ? hy : hx, hm = maj ? hx : hy;
+    const double pd = atan2(hm, hM), ph = atan2(hm, 2.0 * hM);
+    const double cd = cos(pd), sd = sin(pd), ch = cos(ph), sh = sin(ph);
+    in.cc_m[maj][0] = (hM * (1.0 - ch) + hm * (sd - sh) - hM * (ch - cd)) / Atot;
+    in.cc_m[maj][1] = (hm * sh - 2.0 * hM * (1.0 - ch)) / Atot;
+    in.cc_m[maj][2] = (2.0 * hM * (ch - cd) - hm * (sd - sh)) / Atot;
+  }
+  // per-direction totals, summed in the kernels' order so that an interior
+  // cell gets the same weights by either route
+  for (int j = 0; j < 8; ++j) {
+    in.cc_a[j] = 0.0;
+    in.cc_step[j][0] = cc_dx(j) * hx;
+    in.cc_step[j][1] = cc_dy(j) * hy;
+  }
+  cc_pieces([&](int J, int, int, int maj, int mi) { in.cc_a[J] += in.cc_m[maj][mi]; });
+  p->Atot = Atot;
+}
+
 void set_walk(Inst &in, int ndim, const int64_t dims[3], int mseg_override, int vw_override) {
   in.ndim = ndim;
   in.nx = (int32_t)dims[0];
@@ -279,6 +338,11 @@ void set_walk(Inst &in, int ndim, const int64_t dims[3], int mseg_override, int 
   in.nseg = (in.nm + mseg - 1) / mseg;
   in.nwaves = strips * in.nseg;
   in.nblocks = (int32_t)((in.nwaves + kWavesPerBlock - 1) / kWavesPerBlock);
+  if (in.cc) {
+    // the cell-centred kernels take contiguous cell ranges of 2048 cells
+    in.vw = 1;
+    in.nblocks = (int32_t)std::max<int64_t>(1, (in.ncell + 2047) / 2048);
+  }
 }
 
 std::vector<BlockEnt> build_table(const std::vector<Inst *> &insts, int part_base0, int *part_total) {
@@ -311,7 +375,8 @@ hipError_t plan_alloc(pi_plan_s *p, void **ptr, size_t bytes) {
   return e;
 }
 
-// Union-find over face-adjacent data cells (host, once per plan).
+// Union-find over adjacent data cells (host, once per plan): face neighbours,
+// and diagonal ones for the cell-centred scheme.
 static int32_t components(const pi_plan_s *p, const uint8_t *mask, std::vector<int32_t> &label,
                           std::vector<int64_t> &count) {
   const int64_t n = p->ncell;
@@ -341,6 +406,10 @@ static int32_t components(const pi_plan_s *p, const uint8_t *mask, std::vector<i
     const int64_t x = c % nx, y = (c / nx) % ny, z = c / sz;
     if (x + 1 < nx && mask[c + 1]) unite((int32_t)c, (int32_t)(c + 1));
     if (y + 1 < ny && mask[c + sy]) unite((int32_t)c, (int32_t)(c + sy));
+    if (p->cc && y + 1 < ny) {  // the cell-centred scheme couples diagonal neighbours
+      if (x + 1 < nx && mask[c + sy + 1]) unite((int32_t)c, (int32_t)(c + sy + 1));
+      if (x >= 1 && mask[c + sy - 1]) unite((int32_t)c, (int32_t)(c + sy - 1));
+    }
     if (p->ndim == 3 && z + 1 < p->dims[2] && mask[c + sz]) unite((int32_t)c, (int32_t)(c + sz));
   }
   label.assign(n, -1);
@@ -394,8 +463,9 @@ extern "C" pi_status pi_plan(int ndim, const int64_t dims[3], const double spaci
   if (!out) return PI_ERR_INVALID_ARG;
   *out = nullptr;
   if ((ndim != 2 && ndim != 3) || !dims || !spacing) return PI_ERR_INVALID_ARG;
-  if (flags & ~(PI_FP64 | PI_INNER_BICGSTAB | PI_FIXED_POINT_CG)) return PI_ERR_INVALID_ARG;
+  if (flags & ~(PI_FP64 | PI_INNER_BICGSTAB | PI_FIXED_POINT_CG | PI_CELL_CENTERED)) return PI_ERR_INVALID_ARG;
   if ((flags & PI_FIXED_POINT_CG) && (flags & PI_INNER_BICGSTAB)) return PI_ERR_INVALID_ARG;
+  if ((flags & PI_CELL_CENTERED) && (ndim != 2 || (flags & PI_INNER_BICGSTAB))) return PI_ERR_INVALID_ARG;
   int64_t ncell = 1;
   for (int a = 0; a < ndim; ++a) {
     if (dims[a] < 1 || dims[a] >= (int64_t(1) << 31)) return PI_ERR_INVALID_ARG;
@@ -414,6 +484,7 @@ extern "C" pi_status pi_plan(int ndim, const int64_t dims[3], const double spaci
   p->fp64 = (flags & PI_FP64) != 0;
   p->bicgstab = (flags & PI_INNER_BICGSTAB) != 0;
   p->fixed_point = (flags & PI_FIXED_POINT_CG) != 0;
+  p->cc = (flags & PI_CELL_CENTERED) != 0;
   p->ncell = ncell;
   // inner iterations per outer step.  The outer step count falls towards its
   // exact-inner limit (about 16 times the longest side) as k grows, while an
@@ -459,10 +530,15 @@ extern "C" pi_status pi_plan(int ndim, const int64_t dims[3], const double spaci
   const size_t N = (size_t)ncell;
   Inst &in = p->inst;
   memset(&in, 0, sizeof(in));
+  in.cc = p->cc ? 1 : 0;
   set_walk(in, ndim, p->dims, 0, 0);
-  in.gen = mask ? 0 : 1;
+  in.gen = (mask || p->cc) ? 0 : 1;  // the cell-centred kernels always read codes
   in.inner_op = p->fixed_point ? 1 : 0;
+  // relative r.r at which the variant's CG has reached the precision of its
+  // vectors (about a relative residual of 1e-7 in FP32, 1e-13 in FP64)
+  in.inner_floor = p->fixed_point ? (p->fp64 ? 1e-26 : 1e-14) : 0.0;
   fill_luts(p, in);
+  if (p->cc) fill_cc(p, in);
   in.ncomp = p->ncomp;
   in.inv_nvalid = 1.0 / (double)nvalid;
 
@@ -474,7 +550,9 @@ extern "C" pi_status pi_plan(int ndim, const int64_t dims[3], const double spaci
   }
   PI_TRY(plan_alloc(p, (void **)&p->code, N * sizeof(uint32_t)));
   if (hipMemcpy(d_mask, m, N, hipMemcpyHostToDevice) != hipSuccess ||
-      launch_codes(ndim, (int)p->dims[0], (int)p->dims[1], (int)p->dims[2], d_mask, p->code, nullptr) != hipSuccess ||
+      (p->cc ? launch_codes_cc((int)p->dims[0], (int)p->dims[1], d_mask, p->code)
+             : launch_codes(ndim, (int)p->dims[0], (int)p->dims[1], (int)p->dims[2], d_mask, p->code, nullptr)) !=
+          hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     (void)hipFree(d_mask);
     pi_plan_destroy(p);

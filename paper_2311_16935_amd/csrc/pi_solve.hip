@@ -213,7 +213,7 @@ Launcher single_launcher(pi_plan_s *p) {
   L.sts = p->d_state;
   L.part = p->d_part;
   L.count = 1;
-  L.grp[shape_of(p->ndim, p->inst.vw, p->inst.gen)] = Group{p->d_tab, p->ntab};
+  L.grp[shape_of(p->ndim, p->inst.vw, p->inst.gen, p->inst.cc)] = Group{p->d_tab, p->ntab};
   return L;
 }
 
@@ -274,7 +274,7 @@ extern "C" pi_status pi_solve_batched(int64_t count, const pi_plan_t *plans, con
   std::vector<Inst *> by[kShapes];
   std::vector<int64_t> idx[kShapes];
   for (int64_t i = 0; i < count; ++i) {
-    const int g = shape_of(host[i].ndim, host[i].vw, host[i].gen);
+    const int g = shape_of(host[i].ndim, host[i].vw, host[i].gen, host[i].cc);
     by[g].push_back(&host[i]);
     idx[g].push_back(i);
   }
@@ -429,6 +429,10 @@ static std::map<std::array<int64_t, 6>, std::array<int32_t, 2>> g_tune;
 
 extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, void *stream) {
   if (!p || reps < 1) return PI_ERR_INVALID_ARG;
+  if (p->inst.cc) {  // the cell-centred kernels have one decomposition
+    if (mseg_out) *mseg_out = p->inst.mseg;
+    return PI_OK;
+  }
   const std::array<int64_t, 6> key = {p->ndim, p->dims[0], p->dims[1], p->dims[2], p->fp64, p->bicgstab};
   std::array<int32_t, 2> best = {-1, 0};
   {

@@ -79,3 +79,14 @@ def test_plan_argument_checks_fail_before_touching_the_device():
         with pytest.raises(pi.PiError) as e:
             pi.pi_plan(*args)
         assert e.value.status == pi.PI_ERR_INVALID_ARG
+
+
+def test_cell_centered_flag_checks_fail_before_touching_the_device():
+    import paper_2311_16935_amd as pi
+
+    for args in [(3, (5, 5, 5), (1.0, 1.0, 1.0), None, pi.PI_CELL_CENTERED),
+                 (2, (5, 5), (1.0, 1.0), None, pi.PI_CELL_CENTERED | pi.PI_INNER_BICGSTAB),
+                 (2, (5, 5), (1.0, 1.0), None, 0x10)]:
+        with pytest.raises(pi.PiError) as e:
+            pi.pi_plan(*args)
+        assert e.value.status == pi.PI_ERR_INVALID_ARG
