@@ -1163,10 +1163,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Ins
 // ---------------------------------------------------------------------------
 // the 2-D cell-centred scheme: 9-point stencils over contiguous cell ranges
 // ---------------------------------------------------------------------------
-// Each lane takes cells of its block's range; the 8 neighbours come from
-// L1/L2 (the ranges are contiguous, so rows y-1, y, y+1 of a block are read
-// by the same CU).  The ring code of a cell tells which of the 24 cells
-// within two steps hold data.
+// The ring code of a cell tells which of the 24 cells within two steps hold
+// data.  The source (once per solve) and pi_apply take contiguous cell
+// ranges and read the 8 neighbours through L1/L2; the outer and CG kernels
+// below march along y.
 
 // offset of neighbour j in cells
 __device__ inline int64_t cc_off(const Inst &in, int j) { return (int64_t)cc_dx(j) + (int64_t)cc_dy(j) * in.nx; }
@@ -1230,6 +1230,79 @@ __global__ __launch_bounds__(kBlock) void k_source_cc(const BlockEnt *tab, const
   publish<1>(in, part, e.lb, acc);
 }
 
+// The outer and CG kernels march like the face-crossing ones: a wave owns 64
+// consecutive cells of a row and walks its segment of rows.  Rows y-1, y,
+// y+1 of the operand sit in registers; the x neighbours of all three rows
+// come from adjacent lanes, and at the strip ends from one extra value per
+// row (lane 0: west, lane 63: east).  Row y+1 is fetched before row y is
+// computed.
+template <typename V>
+struct CcRow {
+  V v, edge;
+};
+
+// nb[j] for the 8 directions of cc_dir, from the three rows
+template <typename V>
+__device__ inline void cc_neighbours(const CcRow<V> &p, const CcRow<V> &c, const CcRow<V> &n, int lane, V (&nb)[8]) {
+  // selects, not conditional stores: written through references, the two
+  // edge cases merge into one store to a lane-chosen address, which puts
+  // the values in scratch memory
+  auto left = [&](const CcRow<V> &r) {
+    const V v = __shfl_up(r.v, 1, kWave);
+    return lane == 0 ? r.edge : v;
+  };
+  auto right = [&](const CcRow<V> &r) {
+    const V v = __shfl_down(r.v, 1, kWave);
+    return lane == kWave - 1 ? r.edge : v;
+  };
+  const V cl = left(c), cr = right(c), pl = left(p), pr = right(p), nl = left(n), nr = right(n);
+  nb[cc_dir(1, 0)] = cr;
+  nb[cc_dir(-1, 0)] = cl;
+  nb[cc_dir(0, 1)] = n.v;
+  nb[cc_dir(0, -1)] = p.v;
+  nb[cc_dir(1, 1)] = nr;
+  nb[cc_dir(-1, 1)] = nl;
+  nb[cc_dir(1, -1)] = pr;
+  nb[cc_dir(-1, -1)] = pl;
+}
+
+//   load(c) -> V   operand at cell c
+//   body(c, code, centre, nb[8]) -> Out;  store(c, Out)
+template <typename V, typename Out, typename Load, typename Body, typename Store>
+__device__ inline void march_cc(const Walk &wk, Load load, Body body, Store store) {
+  if (wk.m1 <= wk.m0) return;  // uniform over the wave
+  const int lane = threadIdx.x & 63;
+  const bool edgeW = lane == 0 && wk.x > 0, edgeE = lane == kWave - 1 && wk.x + 1 < wk.nx;
+  // a neighbour that does not exist reads the cell itself and is zeroed
+  const int64_t offE = edgeW ? -1 : edgeE ? 1 : 0;
+  const bool hasEdge = edgeW || edgeE;
+  const PI_G uint32_t *code = wk.code;
+  auto fetch = [&](int64_t c) {
+    CcRow<V> r;
+    r.v = load(c);
+    const V e = load(c + offE);
+    r.edge = hasEdge ? e : V(0);
+    return r;
+  };
+  const int64_t sm = wk.sm;
+  int64_t c = wk.base + (int64_t)wk.m0 * sm;
+  CcRow<V> prev = wk.m0 > 0 ? fetch(c - sm) : CcRow<V>{V(0), V(0)};
+  CcRow<V> cur = fetch(c);
+  uint32_t cd = code[c];
+  for (int m = wk.m0; m < wk.m1; ++m, c += sm) {
+    const bool more = m + 1 < wk.nm;  // uniform over the wave
+    const CcRow<V> nxt = more ? fetch(c + sm) : CcRow<V>{V(0), V(0)};
+    const uint32_t cdn = m + 1 < wk.m1 ? code[c + sm] : 0u;
+    V nb[8];
+    cc_neighbours(prev, cur, nxt, lane, nb);
+    // lanes past the grid only serve the shuffles
+    if (wk.act) store(c, body(c, cd, cur.v, nb));
+    prev = cur;
+    cur = nxt;
+    cd = cdn;
+  }
+}
+
 // P' = P + delta (the pending last CG step folded in as in k_outer),
 // r = S - (M - N) P' with (M - N) P' = sum_J a_J (P'_C - P'_J)
 template <typename T>
@@ -1237,43 +1310,43 @@ __global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const 
                                                     double *part) {
   PI_PROLOGUE
   if (skip_outer(st)) return;
-  int64_t beg, end;
-  linear_range(in, e.lb, beg, end);
+  const Walk wk = make_walk<1>(in, e.lb);
   const int cur = st->Pcur;
-  const double *Pold = in.P[cur];
-  double *Pnew = in.P[cur ^ 1];
+  const PI_G double *Pold = gp<double>(in.P[cur]);
+  PI_G double *Pnew = gp<double>(in.P[cur ^ 1]);
   const T at = st->tail ? (T)st->alpha : T(0);
-  const T *pt = (const T *)in.p[st->pcur];
-  const T *dl = (const T *)in.d;
-  const double *S = in.S64;
-  T *res = (T *)in.res;
-  const uint32_t *code = in.code;
+  const PI_G T *pt = gp<T>(in.p[st->pcur]);
+  const PI_G T *dl = gp<T>(in.d);
+  const PI_G double *S = gp<double>(in.S64);
+  PI_G T *res = gp<T>(in.res);
+  double a[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] = in.cc_a[j];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
-    const uint32_t cd = code[c];
-    if (!(cd & kValidBit)) {
-      Pnew[c] = 0.0;
-      res[c] = T(0);
-      continue;
-    }
-    const T dC = dl[c] + at * pt[c];
-    const double vC = Pold[c] + (double)dC;
+  struct Out {
+    double p, r;
+  };
+  auto load = [&](int64_t q) { return Pold[q] + (double)(dl[q] + at * pt[q]); };
+  auto body = [&](int64_t c, uint32_t cd, double vC, const double (&nb)[8]) -> Out {
+    if (!(cd & kValidBit)) return Out{0.0, 0.0};
     double Lp = 0.0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      if (!cc_has(cd, j)) continue;
-      const int64_t q = c + cc_off(in, j);
-      Lp += in.cc_a[j] * (vC - (Pold[q] + (double)(dl[q] + at * pt[q])));
-    }
+    for (int j = 0; j < 8; ++j)
+      if (cc_has(cd, j)) Lp += a[j] * (vC - nb[j]);
+    const double dC = (double)(dl[c] + at * pt[c]);
     const double r = S[c] - Lp;
     const double rt = (double)(T)r;
     acc[0] += r * r;
     acc[1] += rt * rt;
-    acc[2] += (double)dC * (double)dC;
+    acc[2] += dC * dC;
     acc[3] += vC * vC;
-    Pnew[c] = vC;
-    res[c] = (T)r;
-  }
+    return Out{vC, r};
+  };
+  auto store = [&](int64_t c, const Out &o) {
+    Pnew[c] = o.p;
+    res[c] = (T)o.r;
+  };
+  march_cc<double, Out>(wk, load, body, store);
   publish<4>(in, part, e.lb, acc);
 }
 
@@ -1284,34 +1357,24 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv_cc(const BlockEnt *tab, cons
                                                       double *part) {
   PI_PROLOGUE
   if (skip_inner(in, st)) return;
-  int64_t beg, end;
-  linear_range(in, e.lb, beg, end);
+  const Walk wk = make_walk<1>(in, e.lb);
   const T beta = (T)st->beta;
   const int pc = st->pcur;
-  const T *pold = (const T *)in.p[pc];
-  T *pnew = (T *)in.p[pc ^ 1];
-  const T *res = (const T *)in.res;
-  T *q = (T *)in.q;
-  const uint32_t *code = in.code;
+  const PI_G T *pold = gp<T>(in.p[pc]);
+  PI_G T *pnew = gp<T>(in.p[pc ^ 1]);
+  const PI_G T *res = gp<T>(in.res);
+  PI_G T *q = gp<T>(in.q);
   const bool opL = in.inner_op != 0;
   T a[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) a[j] = (T)in.cc_a[j];
   double acc[1] = {0.0};
-  for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
-    const uint32_t cd = code[c];
-    if (!(cd & kValidBit)) {
-      pnew[c] = T(0);
-      q[c] = T(0);
-      continue;
-    }
-    const T pC = res[c] + beta * pold[c];
-    T nb[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int64_t o = c + cc_off(in, j);
-      nb[j] = cc_has(cd, j) ? res[o] + beta * pold[o] : T(0);
-    }
+  struct Out {
+    T p, q;
+  };
+  auto load = [&](int64_t o) { return res[o] + beta * pold[o]; };
+  auto body = [&](int64_t, uint32_t cd, T pC, const T (&nb)[8]) -> Out {
+    if (!(cd & kValidBit)) return Out{T(0), T(0)};
     T s;
     if (opL) {
       s = T(0);
@@ -1327,12 +1390,17 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv_cc(const BlockEnt *tab, cons
       cc_weights(in, cd, np1, wn);
       s = pC;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) s -= (T)np1[j] * nb[j];
+      for (int j = 0; j < 8; ++j)
+        if (cc_has(cd, j)) s -= (T)np1[j] * nb[j];
     }
     acc[0] += (double)pC * (double)s;
-    pnew[c] = pC;
-    q[c] = s;
-  }
+    return Out{pC, s};
+  };
+  auto store = [&](int64_t c, const Out &o) {
+    pnew[c] = o.p;
+    q[c] = o.q;
+  };
+  march_cc<T, Out>(wk, load, body, store);
   publish<1>(in, part, e.lb, acc);
 }
 

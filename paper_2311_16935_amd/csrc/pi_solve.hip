@@ -429,11 +429,8 @@ static std::map<std::array<int64_t, 6>, std::array<int32_t, 2>> g_tune;
 
 extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, void *stream) {
   if (!p || reps < 1) return PI_ERR_INVALID_ARG;
-  if (p->inst.cc) {  // the cell-centred kernels have one decomposition
-    if (mseg_out) *mseg_out = p->inst.mseg;
-    return PI_OK;
-  }
-  const std::array<int64_t, 6> key = {p->ndim, p->dims[0], p->dims[1], p->dims[2], p->fp64, p->bicgstab};
+  const std::array<int64_t, 6> key = {p->ndim, p->dims[0], p->dims[1], p->dims[2], p->fp64,
+                                      (p->bicgstab ? 1 : 0) | (p->cc ? 2 : 0)};
   std::array<int32_t, 2> best = {-1, 0};
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -443,7 +440,8 @@ extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, v
   pi_status rc;
   if (best[0] < 0) {
     std::vector<std::array<int32_t, 2>> cand;
-    const std::vector<int32_t> widths = p->dims[0] % 4 == 0 ? std::vector<int32_t>{4, 1} : std::vector<int32_t>{1};
+    const std::vector<int32_t> widths =
+        p->dims[0] % 4 == 0 && !p->cc ? std::vector<int32_t>{4, 1} : std::vector<int32_t>{1};
     for (int32_t vw : widths) {
       if ((rc = pi_set_tile(p, 0, vw)) != PI_OK) return rc;
       cand.push_back({p->inst.mseg, vw});
