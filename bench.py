@@ -182,7 +182,7 @@ def timed_solve(plan, grads, P, tol, chunk, max_iter=10**7):
             return info
 
 
-def kernel_mode(args, pi, plan, grads, P, ncell):
+def kernel_mode(args, pi, plan, grads, P, ncell, bytes_per_cell=BYTES_PER_CELL):
     """Few dispatches: fill the workspace with four outer steps, then launch
     each outer-step kernel a few times, then run an element-wise int32 kernel
     over ncell elements (reads and writes 4 * ncell bytes) as the counter
@@ -194,8 +194,8 @@ def kernel_mode(args, pi, plan, grads, P, ncell):
     for name, kid in (("k_outer", pi.PI_K_OUTER), ("k_cg_spmv", pi.PI_K_SPMV), ("k_cg_update", pi.PI_K_UPDATE)):
         ms = pi.pi_time_kernel(plan.handle, kid, args.kernel_reps)
         res[name] = {"avg_ms": ms, "launches": args.kernel_reps + 1,
-                     "alg_bytes": BYTES_PER_CELL[name] * ncell,
-                     "achieved_GBs": BYTES_PER_CELL[name] * ncell / (ms * 1e-3) / 1e9}
+                     "alg_bytes": bytes_per_cell[name] * ncell,
+                     "achieved_GBs": bytes_per_cell[name] * ncell / (ms * 1e-3) / 1e9}
     # yardstick with a kernel name nothing else here uses: reads and writes
     # 4 bytes per element
     x = torch.randint(0, 1 << 30, (ncell,), dtype=torch.int32, device="cuda:0")
@@ -205,6 +205,7 @@ def kernel_mode(args, pi, plan, grads, P, ncell):
     torch.cuda.synchronize()
     res["bitwise_not"] = {"bytes_read": 4 * ncell, "bytes_written": 4 * ncell, "launches": args.kernel_reps}
     print(json.dumps({"mode": "kernels", "n": args.n, "cells": ncell, "tile": pi.pi_get_tile(plan.handle),
+                      "workload": args.workload, "cell_centered": bool(args.cell_centered),
                       "kernels": res, "kernel_source_sha256": kernel_source_hash()}), flush=True)
 
 
@@ -596,7 +597,7 @@ def main():
         tune = {"mseg": m, "seconds": time.perf_counter() - t0}
         progress(f"autotuned tile: {m} planes per segment ({tune['seconds']:.1f} s, outside the timed region)")
     if args.mode == "kernels":
-        kernel_mode(args, pi, plan, grads, P, ncell)
+        kernel_mode(args, pi, plan, grads, P, ncell, bytes_per_cell)
         return
     for i in range(args.warmup):
         info = timed_solve(plan, grads, P, args.tol, args.chunk_outer_solve)
@@ -634,12 +635,13 @@ def main():
         kern[name]["share_of_solve"] = launches[name] * kern[name]["avg_ms"] * 1e-3 / sec
     dom = max(kern, key=lambda k: kern[k]["launches_per_solve"] * kern[k]["avg_ms"])
     d = kern[dom]
-    traffic = traffic_from_profile(dom, n, src_hash) if args.workload == "blobs3d" else None
     if cc:
         kern_names = {"k_outer": "k_outer_cc", "k_cg_spmv": "k_cg_spmv_cc"}
         dom_name = kern_names.get(dom, dom)
+        traffic = traffic_from_profile(dom_name, n, src_hash, "lamb_cc")
     else:
         dom_name = dom
+        traffic = traffic_from_profile(dom, n, src_hash) if args.workload == "blobs3d" else None
     roof = {"kernel": dom_name, "bound": "hbm", "achieved": d["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": d["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
             "bytes_per_cell": bytes_per_cell[dom], "cells_per_launch": ncell}
