@@ -174,6 +174,19 @@ __device__ inline uint32_t code_at(int x, int y, int z, int nx, int ny, int nz) 
   return out;
 }
 
+// Code word of a cell whose face neighbours, their laterals and their far
+// cells all hold data: every direction in its last state.
+template <int ND>
+__host__ __device__ constexpr uint32_t interior_code() {
+  uint32_t c = kValidBit;
+  for (int d = 0; d < 2 * ND; ++d) c |= (ND == 3 ? 18u : 6u) << ((ND == 3 ? 5 : 3) * d);
+  return c;
+}
+template <int ND>
+__host__ __device__ constexpr int interior_state() {
+  return ND == 3 ? 18 : 6;
+}
+
 // What the stencil body sees at one cell: its operand value, the y
 // neighbours (3-D only), the extra per-cell input and the code word.
 // Neighbours outside the grid read as 0; internal vectors hold 0 in masked
@@ -221,10 +234,19 @@ __device__ inline void march(const Walk &wk, Load load, Load1 load1, Aux aux, Bo
   auto codes = [&](int64_t c, int m) {
     if constexpr (GEN) {
       Vec<uint32_t, W> v;
+      // cells two or more steps inside the grid on every axis have the
+      // interior code (uniform over the wave except at the strip ends)
+      const bool inner = m >= 2 && m + 2 < wk.nm && wk.x >= 2 && wk.x + W + 1 < wk.nx &&
+                         (ND == 2 || (wk.row >= 2 && wk.row + 2 < wk.ny));
+      if (inner) {
 #pragma unroll
-      for (int k = 0; k < W; ++k)
-        v.e[k] = ND == 3 ? code_at<3>(wk.x + k, wk.row, m, wk.nx, wk.ny, wk.nz)
-                         : code_at<2>(wk.x + k, m, 0, wk.nx, wk.ny, 1);
+        for (int k = 0; k < W; ++k) v.e[k] = interior_code<ND>();
+      } else {
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+          v.e[k] = ND == 3 ? code_at<3>(wk.x + k, wk.row, m, wk.nx, wk.ny, wk.nz)
+                           : code_at<2>(wk.x + k, m, 0, wk.nx, wk.ny, 1);
+      }
       return v;
     } else {
       return ldv<W>(code, c);
@@ -518,17 +540,22 @@ __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Ins
     const uint32_t cd = pl.code;
     if (!(cd & kValidBit)) return Out{0.0, 0.0};
     const double vC = pl.v;
+    // neighbours without data read as 0 and get weight 0: no branches
+    const bool all = cd == interior_code<ND>();
+    double w[6];
+#pragma unroll
+    for (int d = 0; d < 2 * ND; ++d) w[d] = (all || dstate(cd, d, bits)) ? a[d] : 0.0;
     double Lp = 0.0;
-    if (dstate(cd, DE, bits)) Lp += a[DE] * (vC - vE);
-    if (dstate(cd, DW, bits)) Lp += a[DW] * (vC - vW);
+    Lp += w[DE] * (vC - vE);
+    Lp += w[DW] * (vC - vW);
     if (ND == 3) {
-      if (dstate(cd, DN, bits)) Lp += a[DN] * (vC - pl.vN);
-      if (dstate(cd, DS, bits)) Lp += a[DS] * (vC - pl.vS);
-      if (dstate(cd, DF, bits)) Lp += a[DF] * (vC - vN);
-      if (dstate(cd, DB, bits)) Lp += a[DB] * (vC - vP);
+      Lp += w[DN] * (vC - pl.vN);
+      Lp += w[DS] * (vC - pl.vS);
+      Lp += w[DF] * (vC - vN);
+      Lp += w[DB] * (vC - vP);
     } else {
-      if (dstate(cd, DN, bits)) Lp += a[DN] * (vC - vN);
-      if (dstate(cd, DS, bits)) Lp += a[DS] * (vC - vP);
+      Lp += w[DN] * (vC - vN);
+      Lp += w[DS] * (vC - vP);
     }
     const double r = pl.aux.S - Lp;
     const double rt = (double)(T)r;
@@ -557,22 +584,32 @@ __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Ins
 // inner conjugate gradient on M delta = r
 // ---------------------------------------------------------------------------
 // The inner operator [W^{n+1}]: s = v_C - sum_j w_j^{n+1} v_J over face
-// neighbours J holding data, weights from the per-state LUT.
+// neighbours J holding data, weights from the per-state LUT.  State 0 (no
+// data) has weight 0 and such neighbours read as 0, so the sum needs no
+// branches; a cell with the interior code takes the interior weights wi
+// from registers instead of the LUT.
 template <typename T, int ND>
-__device__ inline T apply_m(const T (*lut)[kStates], uint32_t cd, int bits, T vC, T vW, T vE, T vN, T vS, T vP,
-                            T vNx) {
-  T s = vC;
-  int t;
-  if ((t = dstate(cd, DE, bits))) s -= lut[DE][t] * vE;
-  if ((t = dstate(cd, DW, bits))) s -= lut[DW][t] * vW;
-  if (ND == 3) {
-    if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * vN;
-    if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * vS;
-    if ((t = dstate(cd, DF, bits))) s -= lut[DF][t] * vNx;
-    if ((t = dstate(cd, DB, bits))) s -= lut[DB][t] * vP;
+__device__ inline T apply_m(const T (*lut)[kStates], const T *wi, uint32_t cd, int bits, T vC, T vW, T vE, T vN,
+                            T vS, T vP, T vNx) {
+  T w[6];
+  if (cd == interior_code<ND>()) {
+#pragma unroll
+    for (int d = 0; d < 2 * ND; ++d) w[d] = wi[d];
   } else {
-    if ((t = dstate(cd, DN, bits))) s -= lut[DN][t] * vNx;
-    if ((t = dstate(cd, DS, bits))) s -= lut[DS][t] * vP;
+#pragma unroll
+    for (int d = 0; d < 2 * ND; ++d) w[d] = lut[d][dstate(cd, d, bits)];
+  }
+  T s = vC;
+  s -= w[DE] * vE;
+  s -= w[DW] * vW;
+  if (ND == 3) {
+    s -= w[DN] * vN;
+    s -= w[DS] * vS;
+    s -= w[DF] * vNx;
+    s -= w[DB] * vP;
+  } else {
+    s -= w[DN] * vNx;
+    s -= w[DS] * vP;
   }
   return s;
 }
@@ -581,17 +618,21 @@ __device__ inline T apply_m(const T (*lut)[kStates], uint32_t cd, int bits, T vC
 // face neighbours holding data (the PI_FIXED_POINT_CG variant's inner operator).
 template <typename T, int ND>
 __device__ inline T apply_l(const T *a, uint32_t cd, int bits, T vC, T vW, T vE, T vN, T vS, T vP, T vNx) {
+  T w[6];
+  const bool all = cd == interior_code<ND>();
+#pragma unroll
+  for (int d = 0; d < 2 * ND; ++d) w[d] = (all || dstate(cd, d, bits)) ? a[d] : T(0);
   T s = T(0);
-  if (dstate(cd, DE, bits)) s += a[DE] * (vC - vE);
-  if (dstate(cd, DW, bits)) s += a[DW] * (vC - vW);
+  s += w[DE] * (vC - vE);
+  s += w[DW] * (vC - vW);
   if (ND == 3) {
-    if (dstate(cd, DN, bits)) s += a[DN] * (vC - vN);
-    if (dstate(cd, DS, bits)) s += a[DS] * (vC - vS);
-    if (dstate(cd, DF, bits)) s += a[DF] * (vC - vNx);
-    if (dstate(cd, DB, bits)) s += a[DB] * (vC - vP);
+    s += w[DN] * (vC - vN);
+    s += w[DS] * (vC - vS);
+    s += w[DF] * (vC - vNx);
+    s += w[DB] * (vC - vP);
   } else {
-    if (dstate(cd, DN, bits)) s += a[DN] * (vC - vNx);
-    if (dstate(cd, DS, bits)) s += a[DS] * (vC - vP);
+    s += w[DN] * (vC - vNx);
+    s += w[DS] * (vC - vP);
   }
   return s;
 }
@@ -605,6 +646,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const BlockEnt *tab, const I
   if (skip_inner(in, st)) return;
   __shared__ T lut[6][kStates];
   load_lut<T>(in.lut_np1, lut);
+  T wi[6];  // interior weights, as the LUT holds them
+#pragma unroll
+  for (int d = 0; d < 6; ++d) wi[d] = (T)in.lut_np1[d][interior_state<ND>()];
   const Walk wk = make_walk<W>(in, e.lb);
   // beta is 0 on the first iteration and the old direction is finite, so
   // the direction update needs no branch
@@ -637,7 +681,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const BlockEnt *tab, const I
     const T vC = pl.v;
     if (!(cd & kValidBit)) return Out{T(0), T(0)};
     const T s = opL ? apply_l<T, ND>(a, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN)
-                    : apply_m<T, ND>(lut, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN);
+                    : apply_m<T, ND>(lut, wi, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN);
     acc[0] += (double)vC * (double)s;
     return Out{vC, s};
   };
@@ -723,6 +767,9 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_p(const BlockEnt *tab, con
   if (skip_inner(in, st)) return;
   __shared__ T lut[6][kStates];
   load_lut<T>(in.lut_np1, lut);
+  T wi[6];  // interior weights, as the LUT holds them
+#pragma unroll
+  for (int d = 0; d < 6; ++d) wi[d] = (T)in.lut_np1[d][interior_state<ND>()];
   const Walk wk = make_walk<W>(in, e.lb);
   const T beta = (T)st->beta, omega = (T)st->omega;
   const int pc = st->pcur;
@@ -750,7 +797,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_p(const BlockEnt *tab, con
     const uint32_t cd = pl.code;
     const T vC = pl.v;
     if (!(cd & kValidBit)) return Out{T(0), T(0)};
-    const T s = apply_m<T, ND>(lut, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN);
+    const T s = apply_m<T, ND>(lut, wi, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN);
     acc[0] += (double)pl.aux * (double)s;
     return Out{vC, s};
   };
@@ -776,6 +823,9 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_s(const BlockEnt *tab, con
   if (skip_inner(in, st)) return;
   __shared__ T lut[6][kStates];
   load_lut<T>(in.lut_np1, lut);
+  T wi[6];  // interior weights, as the LUT holds them
+#pragma unroll
+  for (int d = 0; d < 6; ++d) wi[d] = (T)in.lut_np1[d][interior_state<ND>()];
   const Walk wk = make_walk<W>(in, e.lb);
   const T alpha = (T)st->alpha;
   const PI_G T *res = gp<T>(in.res);
@@ -802,7 +852,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_s(const BlockEnt *tab, con
     const T vC = pl.v;
     const T vv = pl.aux;
     if (!(cd & kValidBit)) return Out{vv, T(0), T(0)};
-    const T s = apply_m<T, ND>(lut, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN);
+    const T s = apply_m<T, ND>(lut, wi, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN);
     acc[0] += (double)s * (double)vC;
     acc[1] += (double)s * (double)s;
     return Out{vv, vC, s};
