@@ -10,7 +10,7 @@ residual and gauge.  Inputs are generated on the GPU before the timed region.
 Prints one JSON line.  Besides the contract fields it carries
   roofline      HBM roofline of the dominant kernel, its duration measured with
                 HIP events on the library's stream (pi_time_kernel)
-  kernels       the same for the three kernels of an outer step
+  kernels       the same for the two kernels of an outer step
   cpu_baseline  the CPU FP64 oracle (route O1, sparse-LU inner solve) on a
                 bounded sample, scaled to one 256^3 solve
 """
@@ -36,12 +36,11 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 # the two stencil kernels).
 BYTES_PER_CELL = {
     "k_outer": 8 + 4 + 4 + 8 + 8 + 4,   # P, d, p (last CG step folded in), S (FP64) in; P', r out
-    "k_cg_spmv": 4 + 4 + 4 + 4,         # r, p in; p', q out
-    "k_cg_update": 4 * 4 + 2 * 4,       # p, q, r, delta in; delta, r out
+    "k_cg_step": 4 * 4 + 4 * 4,         # r, q, p, delta in; r', q', p', delta out
 }
 # the cell-centred kernels always read the 4-byte ring code of each cell
-BYTES_PER_CELL_CC = {"k_outer": BYTES_PER_CELL["k_outer"] + 4, "k_cg_spmv": BYTES_PER_CELL["k_cg_spmv"] + 4,
-                     "k_cg_update": BYTES_PER_CELL["k_cg_update"]}
+BYTES_PER_CELL_CC = {k: v + 4 for k, v in BYTES_PER_CELL.items()}
+TIMED = (("k_outer", 0), ("k_cg_step", 1))  # names and pi_time_kernel ids (PI_K_OUTER, PI_K_INNER)
 
 
 def parse():
@@ -191,7 +190,7 @@ def kernel_mode(args, pi, plan, grads, P, ncell, bytes_per_cell=BYTES_PER_CELL):
 
     plan.solve(grads, P=P, tol=0.0, max_iter=4, check=False)
     res = {}
-    for name, kid in (("k_outer", pi.PI_K_OUTER), ("k_cg_spmv", pi.PI_K_SPMV), ("k_cg_update", pi.PI_K_UPDATE)):
+    for name, kid in TIMED:
         ms = pi.pi_time_kernel(plan.handle, kid, args.kernel_reps)
         res[name] = {"avg_ms": ms, "launches": args.kernel_reps + 1,
                      "alg_bytes": bytes_per_cell[name] * ncell,
@@ -587,7 +586,7 @@ def main():
     bytes_per_cell = dict(BYTES_PER_CELL_CC if cc else BYTES_PER_CELL)
     if mask is not None and not cc:
         bytes_per_cell["k_outer"] += 4
-        bytes_per_cell["k_cg_spmv"] += 4
+        bytes_per_cell["k_cg_step"] += 4
     progress(f"plan ready: {workload}, tile {pi.pi_get_tile(plan.handle)}, "
              f"{plan.workspace_bytes / 2**30:.2f} GiB, {pi.lib.pi_get_lane_cells(plan.handle)} cells per lane")
     tune = None
@@ -623,20 +622,19 @@ def main():
     # kernel durations, measured with HIP events on the library's stream
     src_hash = kernel_source_hash()
     kern = {}
-    for name, kid in (("k_outer", pi.PI_K_OUTER), ("k_cg_spmv", pi.PI_K_SPMV), ("k_cg_update", pi.PI_K_UPDATE)):
+    for name, kid in TIMED:
         ms = pi.pi_time_kernel(plan.handle, kid, args.kernel_reps)
         alg = bytes_per_cell[name] * ncell
         kern[name] = {"avg_ms": ms, "alg_bytes": alg, "achieved_GBs": alg / (ms * 1e-3) / 1e9}
-    # the last CG iteration of every outer step has no update launch (folded into the outer kernel)
-    launches = {"k_outer": info["outer_iters"] + 1, "k_cg_spmv": info["inner_iters_total"],
-                "k_cg_update": info["inner_iters_total"] - info["outer_iters"]}
+    # one pass per CG iteration; the outer kernel folds in the last one's update
+    launches = {"k_outer": info["outer_iters"] + 1, "k_cg_step": info["inner_iters_total"]}
     for name in kern:
         kern[name]["launches_per_solve"] = launches[name]
         kern[name]["share_of_solve"] = launches[name] * kern[name]["avg_ms"] * 1e-3 / sec
     dom = max(kern, key=lambda k: kern[k]["launches_per_solve"] * kern[k]["avg_ms"])
     d = kern[dom]
     if cc:
-        kern_names = {"k_outer": "k_outer_cc", "k_cg_spmv": "k_cg_spmv_cc"}
+        kern_names = {"k_outer": "k_outer_cc", "k_cg_step": "k_cg_step_cc"}
         dom_name = kern_names.get(dom, dom)
         traffic = traffic_from_profile(dom_name, n, src_hash, "lamb_cc")
     else:

@@ -222,20 +222,21 @@ pi_status pi_apply(pi_plan_t plan, int op, const void *x, void *y, void *stream)
  * `reps` times back to back on `stream`, exactly as the solve launches it
  * (same code, grid and data), bracketed by HIP events recorded on that
  * stream, and return the mean duration per launch in *avg_ms.  kernel is
- * PI_K_OUTER, PI_K_SPMV or PI_K_UPDATE.  Meant to run after a pi_solve on the
- * same plan and gradients (the workspace then holds solve data); it
+ * PI_K_OUTER or PI_K_INNER (CG plans only).  Meant to run after a pi_solve
+ * on the same plan and gradients (the workspace then holds solve data); it
  * overwrites the plan's workspace.  Synchronous.
  */
 #define PI_K_OUTER 0   /* outer residual and update, Eq. ResidualMomentum      */
-#define PI_K_SPMV 1    /* inner search direction and M p                       */
-#define PI_K_UPDATE 2  /* inner correction and residual update                 */
+#define PI_K_INNER 1   /* one inner CG iteration: the previous iteration's
+                          correction and residual update, the new search
+                          direction and M p, in one pass                       */
 pi_status pi_time_kernel(pi_plan_t plan, int kernel, int32_t reps, double *avg_ms, void *stream);
 
 /*
  * pi_autotune -- pick the tile (pi_set_tile) that minimises the time of one
  * outer step of Algorithm 1 for this plan: for each candidate (segment
- * length, cells per lane) it times the outer kernel once and the inner
- * kernels `inner_iters` times
+ * length, cells per lane) it times the outer kernel once and the inner CG
+ * pass `inner_iters` times
  * (pi_time_kernel, `reps` launches each) and keeps the fastest.  Results are
  * cached per (ndim, dims, precision, inner solver) for the life of the process,
  * so later plans of the same shape take the cached tile without timing.  The

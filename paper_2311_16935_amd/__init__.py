@@ -99,7 +99,7 @@ EXPORTED = ("pi_plan", "pi_plan_destroy", "pi_workspace_bytes", "pi_set_inner_it
             "pi_get_tile", "pi_get_lane_cells", "pi_solve",
             "pi_solve_batched", "pi_source", "pi_apply", "pi_time_kernel", "pi_autotune", "pi_status_string")
 
-PI_K_OUTER, PI_K_SPMV, PI_K_UPDATE = 0, 1, 2
+PI_K_OUTER, PI_K_INNER = 0, 1
 
 
 class PiError(RuntimeError):

@@ -147,8 +147,10 @@ struct Inst {
   double *S64;      // source vector, kept in FP64 so that it sums to zero
   void *S;          // optional copy of S in T (pi_source output), else NULL
   void *res;
+  void *res1;       // CG: second residual buffer (ping-pong with res)
   void *p[2];       // search direction, ping-pong
   void *q;
+  void *q1;         // CG: second M p buffer (ping-pong with q)
   void *d;          // correction accumulated by the inner solve
   void *bs[4];      // BiCGStab: rhat, v, s, t
   // per-solve user buffers
@@ -179,7 +181,10 @@ struct State {
   int32_t status;   // pi_status
   int32_t nonfinite;
   int32_t tail;     // CG: the last inner iteration's alpha p is still to be
-                    // added to the correction (the outer kernel does it)
+                    // added to the correction (the next inner pass or the outer
+                    // kernel does it)
+  int32_t rcur;     // CG: current residual buffer (res / res1)
+  int32_t qcur;     // CG: current M p buffer (q / q1)
   int32_t pad;
 };
 

@@ -11,8 +11,7 @@ enum KernelId {
   K_INIT,
   K_SOURCE,
   K_OUTER,
-  K_CG_SPMV,
-  K_CG_UPDATE,
+  K_CG_STEP,
   K_BICG_P,
   K_BICG_S,
   K_BICG_UPDATE,

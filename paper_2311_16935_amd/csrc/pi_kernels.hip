@@ -403,14 +403,18 @@ __global__ __launch_bounds__(kBlock) void k_init(const BlockEnt *tab, const Inst
   double *P = in.P[0];
   T *d = (T *)in.d;
   T *p0 = (T *)in.p[0], *p1 = (T *)in.p[1], *v = (T *)in.bs[1];
+  T *q0 = (T *)in.q, *q1 = (T *)in.q1;
   const uint32_t *code = in.code;
   int bad = 0;
   for (int64_t c = beg + threadIdx.x; c < end; c += kBlock) {
     // no correction before the first outer step, and finite search
-    // directions for the first inner iteration (which scales them by 0)
+    // directions and products for the first inner iteration (which scales
+    // them by 0)
     d[c] = T(0);
     p0[c] = T(0);
     p1[c] = T(0);
+    q0[c] = T(0);
+    if (q1) q1[c] = T(0);
     if (v) v[c] = T(0);
     double x = 0.0;
     if (warm && (code[c] & kValidBit)) {
@@ -499,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Ins
   const PI_G T *pt = gp<T>(in.p[st->pcur]);
   const PI_G T *dl = gp<T>(in.d);
   const PI_G double *S = gp<double>(in.S64);
-  PI_G T *res = gp<T>(in.res);
+  PI_G T *res = gp<T>(st->rcur ? in.res1 : in.res);
   const int bits = dir_bits(ND);
   double a[6];
 #pragma unroll
@@ -637,10 +641,44 @@ __device__ inline T apply_l(const T *a, uint32_t cd, int bits, T vC, T vW, T vE,
   return s;
 }
 
-// p <- r + beta p (or p <- r on the first iteration), q <- A p, p.q with A
-// the inner operator ([W^{n+1}], or the fixed point's for the variant)
+// One inner CG iteration k in a single pass (one global reduction per
+// iteration).  The update of iteration k-1 is folded in:
+//   r_k = r_{k-1} - alpha_{k-1} q_{k-1},   delta_k = delta_{k-1} + alpha_{k-1} p_{k-1},
+//   p_k = r_k + beta_k p_{k-1},            q_k = A p_k,
+// with A = [W^{n+1}] (or the fixed point's operator for the variant).  The
+// stencil needs p_k at the neighbours, so r, q and p are read there and
+// written to the other buffer of each pair.  Reductions: p.q, r.q, q.q, r.r;
+// the finalize takes alpha_k = r.r / p.q and beta_{k+1} from
+// |r_k - alpha_k q_k|^2 = r.r - 2 alpha_k r.q + alpha_k^2 q.q.  The first
+// iteration of an outer step has no update to fold (alpha ignored, beta 0),
+// and the second starts the correction from zero.
+template <typename T>
+struct CgPass {
+  const PI_G T *rold, *qold, *pold;
+  PI_G T *rnew, *qnew, *pnew, *d;
+  T al, be;
+  bool rd_d, wr_d;
+};
+
+template <typename T>
+__device__ inline CgPass<T> cg_pass(const Inst &in, const State *st) {
+  CgPass<T> c;
+  c.rold = gp<T>(st->rcur ? in.res1 : in.res);
+  c.rnew = gp<T>(st->rcur ? in.res : in.res1);
+  c.qold = gp<T>(st->qcur ? in.q1 : in.q);
+  c.qnew = gp<T>(st->qcur ? in.q : in.q1);
+  c.pold = gp<T>(in.p[st->pcur]);
+  c.pnew = gp<T>(in.p[st->pcur ^ 1]);
+  c.d = gp<T>(in.d);
+  c.al = st->inner > 0 ? (T)st->alpha : T(0);
+  c.be = (T)st->beta;
+  c.wr_d = st->inner > 0;
+  c.rd_d = st->inner > 1;
+  return c;
+}
+
 template <typename T, int ND, int W, bool GEN>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_cg_step(const BlockEnt *tab, const Inst *insts, State *sts,
                                                     double *part) {
   PI_PROLOGUE
   if (skip_inner(in, st)) return;
@@ -650,110 +688,64 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv(const BlockEnt *tab, const I
 #pragma unroll
   for (int d = 0; d < 6; ++d) wi[d] = (T)in.lut_np1[d][interior_state<ND>()];
   const Walk wk = make_walk<W>(in, e.lb);
-  // beta is 0 on the first iteration and the old direction is finite, so
-  // the direction update needs no branch
-  const T beta = (T)st->beta;
-  const int pc = st->pcur;
-  const PI_G T *pold = gp<T>(in.p[pc]);
-  PI_G T *pnew = gp<T>(in.p[pc ^ 1]);
-  const PI_G T *res = gp<T>(in.res);
-  PI_G T *q = gp<T>(in.q);
+  const CgPass<T> cg = cg_pass<T>(in, st);
   const int bits = dir_bits(ND);
   const bool opL = in.inner_op != 0;  // uniform over the launch
   T a[6];
 #pragma unroll
   for (int d = 0; d < 6; ++d) a[d] = (T)in.a[d];
-  double acc[1] = {0.0};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  struct Aux {
+    T r, d;
+  };
   struct Out {
-    T p, q;
+    T p, q, r, d;
   };
   auto load = [&](int64_t c) {
-    const Vec<T, W> r = ldv<W>(res, c), p = ldv<W>(pold, c);
+    const Vec<T, W> r = ldv<W>(cg.rold, c), q = ldv<W>(cg.qold, c), p = ldv<W>(cg.pold, c);
     Vec<T, W> v;
 #pragma unroll
-    for (int k = 0; k < W; ++k) v.e[k] = r.e[k] + beta * p.e[k];
+    for (int k = 0; k < W; ++k) v.e[k] = (r.e[k] - cg.al * q.e[k]) + cg.be * p.e[k];
     return v;
   };
-  auto load1 = [&](int64_t c) -> T { return res[c] + beta * pold[c]; };
-  auto aux = [](int64_t) { return Vec<int, W>{}; };
-  auto body = [&](int64_t, const Cell<T, int> &pl, T vW, T vE, T vP, T vN) -> Out {
+  auto load1 = [&](int64_t c) -> T { return (cg.rold[c] - cg.al * cg.qold[c]) + cg.be * cg.pold[c]; };
+  auto aux = [&](int64_t c) {
+    const Vec<T, W> r = ldv<W>(cg.rold, c), q = ldv<W>(cg.qold, c), p = ldv<W>(cg.pold, c);
+    const Vec<T, W> d = cg.rd_d ? ldv<W>(cg.d, c) : vzero<T, W>();
+    Vec<Aux, W> x;
+#pragma unroll
+    for (int k = 0; k < W; ++k) x.e[k] = Aux{r.e[k] - cg.al * q.e[k], d.e[k] + cg.al * p.e[k]};
+    return x;
+  };
+  auto body = [&](int64_t, const Cell<T, Aux> &pl, T vW, T vE, T vP, T vN) -> Out {
     const uint32_t cd = pl.code;
     const T vC = pl.v;
-    if (!(cd & kValidBit)) return Out{T(0), T(0)};
+    if (!(cd & kValidBit)) return Out{T(0), T(0), T(0), T(0)};
     const T s = opL ? apply_l<T, ND>(a, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN)
                     : apply_m<T, ND>(lut, wi, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN);
-    acc[0] += (double)vC * (double)s;
-    return Out{vC, s};
+    const double r = (double)pl.aux.r, q = (double)s;
+    acc[0] += (double)vC * q;
+    acc[1] += r * q;
+    acc[2] += q * q;
+    acc[3] += r * r;
+    return Out{vC, s, pl.aux.r, pl.aux.d};
   };
   auto store = [&](int64_t c, const Out (&o)[W]) {
-    Vec<T, W> pv, qv;
+    Vec<T, W> pv, qv, rv, dv;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
       pv.e[k] = o[k].p;
       qv.e[k] = o[k].q;
+      rv.e[k] = o[k].r;
+      dv.e[k] = o[k].d;
     }
-    stv<W>(pnew, c, pv);
-    stv<W>(q, c, qv);
+    stv<W>(cg.pnew, c, pv);
+    stv<W>(cg.qnew, c, qv);
+    stv<W>(cg.rnew, c, rv);
+    if (cg.wr_d) stv<W>(cg.d, c, dv);
   };
-  march<ND, W, GEN, T, int, Out>(wk, load, load1, aux, body, store);
-  publish<1>(in, part, e.lb, acc);
-}
-
-// delta <- delta + alpha p (delta <- alpha p on the first iteration),
-// r <- r - alpha q, r.r
-template <typename T>
-struct CgUpdate {
-  static constexpr int E = 16 / sizeof(T);
-  static constexpr int U = 2;
-  const PI_G T *p, *q;
-  PI_G T *res, *d;
-  T alpha;
-  bool first;
-  double acc;
-  Vec<T, E> pv[U], qv[U], rv[U], dv[U];
-  __device__ void load(int64_t c, int u) {
-    pv[u] = ldv<E>(p, c);
-    qv[u] = ldv<E>(q, c);
-    rv[u] = ldv<E>(res, c);
-    dv[u] = first ? vzero<T, E>() : ldv<E>(d, c);
-  }
-  __device__ void apply(int64_t c, int u) {
-    Vec<T, E> r, dn;
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-      r.e[k] = rv[u].e[k] - alpha * qv[u].e[k];
-      dn.e[k] = dv[u].e[k] + alpha * pv[u].e[k];
-      acc += (double)r.e[k] * (double)r.e[k];
-    }
-    stv<E>(d, c, dn);
-    stv<E>(res, c, r);
-  }
-  __device__ void one(int64_t c) {
-    const T r = res[c] - alpha * q[c];
-    d[c] = (first ? T(0) : d[c]) + alpha * p[c];
-    res[c] = r;
-    acc += (double)r * (double)r;
-  }
-};
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_update(const BlockEnt *tab, const Inst *insts, State *sts,
-                                                      double *part) {
-  PI_PROLOGUE
-  if (skip_inner(in, st)) return;
-  int64_t beg, end;
-  linear_range(in, e.lb, beg, end);
-  CgUpdate<T> f;
-  f.p = gp<T>(in.p[st->pcur]);
-  f.q = gp<T>(in.q);
-  f.res = gp<T>(in.res);
-  f.d = gp<T>(in.d);
-  f.alpha = (T)st->alpha;
-  f.first = st->inner == 0;
-  f.acc = 0.0;
-  stream_linear<CgUpdate<T>::E, CgUpdate<T>::U>(beg, end, f);
-  double acc[1] = {f.acc};
-  publish<1>(in, part, e.lb, acc);
+  march<ND, W, GEN, T, Aux, Out>(wk, load, load1, aux, body, store);
+  publish<4>(in, part, e.lb, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1086,20 +1078,19 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
       }
       break;
     }
-    case K_CG_SPMV:
-      st->alpha = s[0] != 0.0 ? st->rr / s[0] : 0.0;
+    case K_CG_STEP: {
+      const double pq = s[0], rq = s[1], qq = s[2], rr = s[3];
+      const double al = pq != 0.0 ? rr / pq : 0.0;
+      double rn = rr - 2.0 * al * rq + al * al * qq;  // |r_k - alpha_k q_k|^2
+      if (!(rn > 0.0)) rn = 0.0;
+      st->alpha = al;
+      st->beta = rr != 0.0 ? rn / rr : 0.0;
+      st->rr = rn;
       st->pcur ^= 1;
+      st->qcur ^= 1;
+      st->rcur ^= 1;
       st->first = 0;
-      if (st->inner + 1 >= in.inner_iters) {
-        // last inner iteration: its update is left to the outer kernel
-        st->tail = 1;
-        st->inner += 1;
-        st->inner_total += 1;
-      }
-      break;
-    case K_CG_UPDATE:
-      st->beta = st->rr != 0.0 ? s[0] / st->rr : 0.0;
-      st->rr = s[0];
+      st->tail = 1;  // alpha_k p_k is pending: the next pass or the outer kernel adds it
       st->inner += 1;
       st->inner_total += 1;
       // fixed-point variant: the inner residual is the outer residual of
@@ -1109,10 +1100,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
       // rounding-level constant part is left, which the singular operator
       // cannot reduce (p.q -> 0 and alpha would blow up); the next outer
       // step restarts from the FP64 residual
-      if (in.inner_op != 0 &&
-          (s[0] <= 0.25 * in.tol * in.tol * st->normS2 || s[0] <= in.inner_floor * st->rr0))
+      if (in.inner_op != 0 && (rn <= 0.25 * in.tol * in.tol * st->normS2 || rn <= in.inner_floor * st->rr0))
         st->inner = in.inner_iters;
       break;
+    }
     case K_BICG_P:
       st->alpha = s[0] != 0.0 ? st->rho / s[0] : 0.0;
       st->pcur ^= 1;
@@ -1368,7 +1359,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const 
   const PI_G T *pt = gp<T>(in.p[st->pcur]);
   const PI_G T *dl = gp<T>(in.d);
   const PI_G double *S = gp<double>(in.S64);
-  PI_G T *res = gp<T>(in.res);
+  PI_G T *res = gp<T>(st->rcur ? in.res1 : in.res);
   double a[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) a[j] = in.cc_a[j];
@@ -1400,31 +1391,26 @@ __global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const 
   publish<4>(in, part, e.lb, acc);
 }
 
-// p <- r + beta p, q <- A p, p.q with A = [W^{n+1}] (or the fixed point's
-// operator for the variant)
+// One inner CG iteration with the previous one's update folded in, as
+// k_cg_step, for the cell-centred scheme.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_spmv_cc(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_cg_step_cc(const BlockEnt *tab, const Inst *insts, State *sts,
                                                       double *part) {
   PI_PROLOGUE
   if (skip_inner(in, st)) return;
   const Walk wk = make_walk<1>(in, e.lb);
-  const T beta = (T)st->beta;
-  const int pc = st->pcur;
-  const PI_G T *pold = gp<T>(in.p[pc]);
-  PI_G T *pnew = gp<T>(in.p[pc ^ 1]);
-  const PI_G T *res = gp<T>(in.res);
-  PI_G T *q = gp<T>(in.q);
+  const CgPass<T> cg = cg_pass<T>(in, st);
   const bool opL = in.inner_op != 0;
   T a[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) a[j] = (T)in.cc_a[j];
-  double acc[1] = {0.0};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   struct Out {
-    T p, q;
+    T p, q, r, d;
   };
-  auto load = [&](int64_t o) { return res[o] + beta * pold[o]; };
-  auto body = [&](int64_t, uint32_t cd, T pC, const T (&nb)[8]) -> Out {
-    if (!(cd & kValidBit)) return Out{T(0), T(0)};
+  auto load = [&](int64_t o) { return (cg.rold[o] - cg.al * cg.qold[o]) + cg.be * cg.pold[o]; };
+  auto body = [&](int64_t c, uint32_t cd, T pC, const T (&nb)[8]) -> Out {
+    if (!(cd & kValidBit)) return Out{T(0), T(0), T(0), T(0)};
     T s;
     if (opL) {
       s = T(0);
@@ -1443,15 +1429,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_spmv_cc(const BlockEnt *tab, cons
       for (int j = 0; j < 8; ++j)
         if (cc_has(cd, j)) s -= (T)np1[j] * nb[j];
     }
-    acc[0] += (double)pC * (double)s;
-    return Out{pC, s};
+    const T rC = cg.rold[c] - cg.al * cg.qold[c];
+    const T dC = (cg.rd_d ? cg.d[c] : T(0)) + cg.al * cg.pold[c];
+    const double r = (double)rC, q = (double)s;
+    acc[0] += (double)pC * q;
+    acc[1] += r * q;
+    acc[2] += q * q;
+    acc[3] += r * r;
+    return Out{pC, s, rC, dC};
   };
   auto store = [&](int64_t c, const Out &o) {
-    pnew[c] = o.p;
-    q[c] = o.q;
+    cg.pnew[c] = o.p;
+    cg.qnew[c] = o.q;
+    cg.rnew[c] = o.r;
+    if (cg.wr_d) cg.d[c] = o.d;
   };
   march_cc<T, Out>(wk, load, body, store);
-  publish<1>(in, part, e.lb, acc);
+  publish<4>(in, part, e.lb, acc);
 }
 
 // y = M x, N x or (M - N) x for pi_apply
@@ -1541,8 +1535,7 @@ static hipError_t launch_t(KernelId k, int shape, const LaunchArgs &la) {
       else k_source<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
       break;
     case K_OUTER: PI_MARCH(k_outer, PI_ARGS); break;
-    case K_CG_SPMV: PI_MARCH(k_cg_spmv, PI_ARGS); break;
-    case K_CG_UPDATE: k_cg_update<T><<<grid, block, 0, s>>>(PI_ARGS); break;
+    case K_CG_STEP: PI_MARCH(k_cg_step, PI_ARGS); break;
     case K_BICG_P:
       if (shape == kShapeCC) return hipErrorInvalidValue;  // CG only
       PI_MARCH8(k_bicg_spmv_p, PI_ARGS);
@@ -1571,8 +1564,7 @@ bool reduces(KernelId k) {
   switch (k) {
     case K_SOURCE:
     case K_OUTER:
-    case K_CG_SPMV:
-    case K_CG_UPDATE:
+    case K_CG_STEP:
     case K_BICG_P:
     case K_BICG_S:
     case K_BICG_UPDATE:

@@ -37,7 +37,7 @@ struct pi_plan_s {
   double *seg_sum = nullptr;
   double *P[2] = {nullptr, nullptr};
   double *S64 = nullptr;
-  void *res = nullptr, *q = nullptr, *d = nullptr;
+  void *res = nullptr, *q = nullptr, *d = nullptr, *res1 = nullptr, *q1 = nullptr;
   void *p[2] = {nullptr, nullptr};
   void *bs[4] = {nullptr, nullptr, nullptr, nullptr};
 

@@ -613,6 +613,10 @@ extern "C" pi_status pi_plan(int ndim, const int64_t dims[3], const double spaci
   PI_TRY(plan_alloc(p, &p->p[1], N * T));
   PI_TRY(plan_alloc(p, &p->q, N * T));
   PI_TRY(plan_alloc(p, &p->d, N * T));
+  if (!p->bicgstab) {  // CG ping-pongs its residual and M p
+    PI_TRY(plan_alloc(p, &p->res1, N * T));
+    PI_TRY(plan_alloc(p, &p->q1, N * T));
+  }
   if (p->bicgstab)
     for (int i = 0; i < 4; ++i) PI_TRY(plan_alloc(p, &p->bs[i], N * T));
   in.P[0] = p->P[0];
@@ -623,6 +627,8 @@ extern "C" pi_status pi_plan(int ndim, const int64_t dims[3], const double spaci
   in.p[0] = p->p[0];
   in.p[1] = p->p[1];
   in.q = p->q;
+  in.q1 = p->q1;
+  in.res1 = p->res1;
   in.d = p->d;
   for (int i = 0; i < 4; ++i) in.bs[i] = p->bs[i];
 
@@ -651,7 +657,7 @@ extern "C" void pi_plan_destroy(pi_plan_t p) {
   if (p->graph) (void)hipGraphExecDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   void *ptrs[] = {p->code, p->label, p->comp_inv, p->comp_sum, p->comp_order, p->seg_begin, p->comp_seg,
-                  p->seg_sum, p->P[0], p->P[1], p->S64, p->res, p->q,
+                  p->seg_sum, p->P[0], p->P[1], p->S64, p->res, p->q, p->res1, p->q1,
                   p->d, p->p[0], p->p[1], p->bs[0], p->bs[1], p->bs[2], p->bs[3], p->d_inst, p->d_state,
                   p->d_tab, p->d_part};
   for (void *q : ptrs)

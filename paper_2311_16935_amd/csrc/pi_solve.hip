@@ -64,9 +64,9 @@ struct Launcher {
           if ((e = go(K_BICG_S, s)) != hipSuccess) return e;
           if ((e = go(K_BICG_UPDATE, s)) != hipSuccess) return e;
         } else {
-          // the last iteration's update is folded into the next outer kernel
-          if ((e = go(K_CG_SPMV, s)) != hipSuccess) return e;
-          if (i + 1 < inner && (e = go(K_CG_UPDATE, s)) != hipSuccess) return e;
+          // one pass per CG iteration; each folds in the previous one's
+          // update, and the outer kernel folds in the last one's
+          if ((e = go(K_CG_STEP, s)) != hipSuccess) return e;
         }
       }
     }
@@ -380,7 +380,8 @@ extern "C" pi_status pi_apply(pi_plan_t p, int op, const void *x, void *y, void 
 }
 
 extern "C" pi_status pi_time_kernel(pi_plan_t p, int kernel, int32_t reps, double *avg_ms, void *stream_) {
-  if (!p || !avg_ms || reps < 1 || kernel < PI_K_OUTER || kernel > PI_K_UPDATE) return PI_ERR_INVALID_ARG;
+  if (!p || !avg_ms || reps < 1 || (kernel != PI_K_OUTER && kernel != PI_K_INNER)) return PI_ERR_INVALID_ARG;
+  if (kernel == PI_K_INNER && p->bicgstab) return PI_ERR_INVALID_ARG;
   hipStream_t stream = (hipStream_t)stream_;
   const Launcher L = single_launcher(p);
   // a mid-solve state: a correction is pending, the search direction is not
@@ -392,12 +393,13 @@ extern "C" pi_status pi_time_kernel(pi_plan_t p, int kernel, int32_t reps, doubl
   State st = fresh_state();
   st.first = 0;
   st.have_delta = 1;
-  st.inner = 1;
+  st.tail = 1;
+  st.inner = 2;  // a pass that reads and writes the correction
   st.rr = 1.0;
   st.alpha = 1e-3;
   st.beta = 0.5;
   st.normS2 = 1.0;
-  const KernelId k = kernel == PI_K_OUTER ? K_OUTER : kernel == PI_K_SPMV ? K_CG_SPMV : K_CG_UPDATE;
+  const KernelId k = kernel == PI_K_OUTER ? K_OUTER : K_CG_STEP;
   hipEvent_t a = nullptr, b = nullptr;
   pi_status rc = PI_ERR_DEVICE;
   float ms = 0.f;
@@ -451,12 +453,11 @@ extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, v
     double best_ms = 1e300;
     for (const auto &c : cand) {
       if ((rc = pi_set_tile(p, c[0], c[1])) != PI_OK) return rc;
-      double t_outer = 0.0, t_spmv = 0.0, t_upd = 0.0;
+      double t_outer = 0.0, t_inner = 0.0;
       if ((rc = pi_time_kernel(p, PI_K_OUTER, reps, &t_outer, stream)) != PI_OK ||
-          (rc = pi_time_kernel(p, PI_K_SPMV, reps, &t_spmv, stream)) != PI_OK ||
-          (rc = pi_time_kernel(p, PI_K_UPDATE, reps, &t_upd, stream)) != PI_OK)
+          (!p->bicgstab && (rc = pi_time_kernel(p, PI_K_INNER, reps, &t_inner, stream)) != PI_OK))
         return rc;
-      const double step = t_outer + p->inner_iters * t_spmv + (p->inner_iters - 1) * t_upd;
+      const double step = t_outer + p->inner_iters * t_inner;
       if (step < best_ms) {
         best_ms = step;
         best = {p->inst.mseg, p->inst.vw};
