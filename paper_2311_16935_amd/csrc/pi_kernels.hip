@@ -1308,9 +1308,10 @@ __device__ inline void cc_neighbours(const CcRow<V> &p, const CcRow<V> &c, const
 }
 
 //   load(c) -> V   operand at cell c
-//   body(c, code, centre, nb[8]) -> Out;  store(c, Out)
-template <typename V, typename Out, typename Load, typename Body, typename Store>
-__device__ inline void march_cc(const Walk &wk, Load load, Body body, Store store) {
+//   aux(c)  -> A   extra input of cell c, fetched with the operand one row ahead
+//   body(c, code, centre, nb[8], aux) -> Out;  store(c, Out)
+template <typename V, typename A, typename Out, typename Load, typename Aux, typename Body, typename Store>
+__device__ inline void march_cc(const Walk &wk, Load load, Aux aux, Body body, Store store) {
   if (wk.m1 <= wk.m0) return;  // uniform over the wave
   const int lane = threadIdx.x & 63;
   const bool edgeW = lane == 0 && wk.x > 0, edgeE = lane == kWave - 1 && wk.x + 1 < wk.nx;
@@ -1330,17 +1331,21 @@ __device__ inline void march_cc(const Walk &wk, Load load, Body body, Store stor
   CcRow<V> prev = wk.m0 > 0 ? fetch(c - sm) : CcRow<V>{V(0), V(0)};
   CcRow<V> cur = fetch(c);
   uint32_t cd = code[c];
+  A ax = aux(c);
   for (int m = wk.m0; m < wk.m1; ++m, c += sm) {
     const bool more = m + 1 < wk.nm;  // uniform over the wave
+    const bool own = m + 1 < wk.m1;   // the next row is this wave's too
     const CcRow<V> nxt = more ? fetch(c + sm) : CcRow<V>{V(0), V(0)};
-    const uint32_t cdn = m + 1 < wk.m1 ? code[c + sm] : 0u;
+    const uint32_t cdn = own ? code[c + sm] : 0u;
+    const A axn = own ? aux(c + sm) : A{};
     V nb[8];
     cc_neighbours(prev, cur, nxt, lane, nb);
     // lanes past the grid only serve the shuffles
-    if (wk.act) store(c, body(c, cd, cur.v, nb));
+    if (wk.act) store(c, body(c, cd, cur.v, nb, ax));
     prev = cur;
     cur = nxt;
     cd = cdn;
+    ax = axn;
   }
 }
 
@@ -1368,7 +1373,9 @@ __global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const 
     double p, r;
   };
   auto load = [&](int64_t q) { return Pold[q] + (double)(dl[q] + at * pt[q]); };
-  auto body = [&](int64_t c, uint32_t cd, double vC, const double (&nb)[8]) -> Out {
+  struct None {};
+  auto aux = [](int64_t) { return None{}; };
+  auto body = [&](int64_t c, uint32_t cd, double vC, const double (&nb)[8], None) -> Out {
     if (!(cd & kValidBit)) return Out{0.0, 0.0};
     double Lp = 0.0;
 #pragma unroll
@@ -1387,7 +1394,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const 
     Pnew[c] = o.p;
     res[c] = (T)o.r;
   };
-  march_cc<double, Out>(wk, load, body, store);
+  march_cc<double, None, Out>(wk, load, aux, body, store);
   publish<4>(in, part, e.lb, acc);
 }
 
@@ -1409,7 +1416,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_step_cc(const BlockEnt *tab, cons
     T p, q, r, d;
   };
   auto load = [&](int64_t o) { return (cg.rold[o] - cg.al * cg.qold[o]) + cg.be * cg.pold[o]; };
-  auto body = [&](int64_t c, uint32_t cd, T pC, const T (&nb)[8]) -> Out {
+  struct Aux {
+    T r, d;
+  };
+  auto aux = [&](int64_t c) {
+    return Aux{cg.rold[c] - cg.al * cg.qold[c], (cg.rd_d ? cg.d[c] : T(0)) + cg.al * cg.pold[c]};
+  };
+  auto body = [&](int64_t c, uint32_t cd, T pC, const T (&nb)[8], const Aux &ax) -> Out {
     if (!(cd & kValidBit)) return Out{T(0), T(0), T(0), T(0)};
     T s;
     if (opL) {
@@ -1429,8 +1442,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_step_cc(const BlockEnt *tab, cons
       for (int j = 0; j < 8; ++j)
         if (cc_has(cd, j)) s -= (T)np1[j] * nb[j];
     }
-    const T rC = cg.rold[c] - cg.al * cg.qold[c];
-    const T dC = (cg.rd_d ? cg.d[c] : T(0)) + cg.al * cg.pold[c];
+    const T rC = ax.r, dC = ax.d;
     const double r = (double)rC, q = (double)s;
     acc[0] += (double)pC * q;
     acc[1] += r * q;
@@ -1444,7 +1456,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_step_cc(const BlockEnt *tab, cons
     cg.rnew[c] = o.r;
     if (cg.wr_d) cg.d[c] = o.d;
   };
-  march_cc<T, Out>(wk, load, body, store);
+  march_cc<T, Aux, Out>(wk, load, aux, body, store);
   publish<4>(in, part, e.lb, acc);
 }
 
