@@ -28,15 +28,16 @@ constexpr int kXcd = 8;
 constexpr uint32_t kValidBit = 1u << 31;
 constexpr int kStates = 20;      // per-direction counter states (3-D uses 0..18)
 constexpr int kSegCells = 65536; // gauge segment length (cells)
-constexpr int kShapes = 9;       // stencil launch shapes: (2-D, 3-D) x (1, 4 cells per lane) x (codes read,
-                                 // derived), and the 2-D cell-centred scheme
+constexpr int kShapes = 10;      // stencil launch shapes: (2-D, 3-D) x (1, 4 cells per lane) x (codes read,
+                                 // derived), and the 2-D cell-centred scheme with 1 or 4 cells per lane
 constexpr int kShapeCC = 8;
+constexpr int kShapeCC4 = 9;
 
 // Launch shape of an instance: bit 0 = 3-D, bit 1 = four cells per lane,
 // bit 2 = no mask (counter codes derived from cell coordinates); the
 // cell-centred scheme has a shape of its own.
 __host__ __device__ inline int shape_of(int ndim, int vw, int gen, int cc) {
-  if (cc) return kShapeCC;
+  if (cc) return vw == 4 ? kShapeCC4 : kShapeCC;
   return (ndim == 3 ? 1 : 0) | (vw == 4 ? 2 : 0) | (gen ? 4 : 0);
 }
 

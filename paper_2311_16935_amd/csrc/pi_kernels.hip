@@ -1277,71 +1277,94 @@ __global__ __launch_bounds__(kBlock) void k_source_cc(const BlockEnt *tab, const
 // come from adjacent lanes, and at the strip ends from one extra value per
 // row (lane 0: west, lane 63: east).  Row y+1 is fetched before row y is
 // computed.
-template <typename V>
+template <int W, typename V>
 struct CcRow {
-  V v, edge;
+  Vec<V, W> v;
+  V edge;
 };
 
-// nb[j] for the 8 directions of cc_dir, from the three rows
-template <typename V>
-__device__ inline void cc_neighbours(const CcRow<V> &p, const CcRow<V> &c, const CcRow<V> &n, int lane, V (&nb)[8]) {
-  // selects, not conditional stores: written through references, the two
-  // edge cases merge into one store to a lane-chosen address, which puts
-  // the values in scratch memory
-  auto left = [&](const CcRow<V> &r) {
-    const V v = __shfl_up(r.v, 1, kWave);
-    return lane == 0 ? r.edge : v;
-  };
-  auto right = [&](const CcRow<V> &r) {
-    const V v = __shfl_down(r.v, 1, kWave);
-    return lane == kWave - 1 ? r.edge : v;
-  };
-  const V cl = left(c), cr = right(c), pl = left(p), pr = right(p), nl = left(n), nr = right(n);
-  nb[cc_dir(1, 0)] = cr;
-  nb[cc_dir(-1, 0)] = cl;
-  nb[cc_dir(0, 1)] = n.v;
-  nb[cc_dir(0, -1)] = p.v;
-  nb[cc_dir(1, 1)] = nr;
-  nb[cc_dir(-1, 1)] = nl;
-  nb[cc_dir(1, -1)] = pr;
-  nb[cc_dir(-1, -1)] = pl;
+// x neighbours of a row's W cells: inside the lane, from the adjacent
+// lanes across lane boundaries, from the edge value at the strip ends.
+// Selects, not conditional stores: written through references, edge cases
+// merge into one store to a lane-chosen address, which puts the values in
+// scratch memory.
+template <int W, typename V>
+__device__ inline void cc_sides(const CcRow<W, V> &r, int lane, V (&l)[W], V (&rt)[W]) {
+  const V up = __shfl_up(r.v.e[W - 1], 1, kWave);
+  const V dn = __shfl_down(r.v.e[0], 1, kWave);
+  const V l0 = lane == 0 ? r.edge : up;
+  const V rw = lane == kWave - 1 ? r.edge : dn;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    l[k] = k == 0 ? l0 : r.v.e[k > 0 ? k - 1 : 0];
+    rt[k] = k == W - 1 ? rw : r.v.e[k + 1 < W ? k + 1 : 0];
+  }
 }
 
-//   load(c) -> V   operand at cell c
-//   aux(c)  -> A   extra input of cell c, fetched with the operand one row ahead
-//   body(c, code, centre, nb[8], aux) -> Out;  store(c, Out)
-template <typename V, typename A, typename Out, typename Load, typename Aux, typename Body, typename Store>
-__device__ inline void march_cc(const Walk &wk, Load load, Aux aux, Body body, Store store) {
+//   load(c) -> Vec<V, W>   operand at cells c .. c+W-1;  load1(c) -> V  one cell
+//   aux(c)  -> Vec<A, W>   extra input of the cells, fetched with the operand one row ahead
+//   body(c, code, centre, nb[8], aux) -> Out;  store(c, const Out (&)[W])
+template <int W, typename V, typename A, typename Out, typename Load, typename Load1, typename Aux, typename Body,
+          typename Store>
+__device__ inline void march_cc(const Walk &wk, Load load, Load1 load1, Aux aux, Body body, Store store) {
   if (wk.m1 <= wk.m0) return;  // uniform over the wave
   const int lane = threadIdx.x & 63;
-  const bool edgeW = lane == 0 && wk.x > 0, edgeE = lane == kWave - 1 && wk.x + 1 < wk.nx;
+  const bool edgeW = lane == 0 && wk.x > 0, edgeE = lane == kWave - 1 && wk.x + W < wk.nx;
   // a neighbour that does not exist reads the cell itself and is zeroed
-  const int64_t offE = edgeW ? -1 : edgeE ? 1 : 0;
+  const int64_t offE = edgeW ? -1 : edgeE ? W : 0;
   const bool hasEdge = edgeW || edgeE;
   const PI_G uint32_t *code = wk.code;
   auto fetch = [&](int64_t c) {
-    CcRow<V> r;
+    CcRow<W, V> r;
     r.v = load(c);
-    const V e = load(c + offE);
+    const V e = load1(c + offE);
     r.edge = hasEdge ? e : V(0);
+    return r;
+  };
+  auto none = [] {
+    CcRow<W, V> r;
+    r.v = vzero<V, W>();
+    r.edge = V(0);
     return r;
   };
   const int64_t sm = wk.sm;
   int64_t c = wk.base + (int64_t)wk.m0 * sm;
-  CcRow<V> prev = wk.m0 > 0 ? fetch(c - sm) : CcRow<V>{V(0), V(0)};
-  CcRow<V> cur = fetch(c);
-  uint32_t cd = code[c];
-  A ax = aux(c);
+  CcRow<W, V> prev = wk.m0 > 0 ? fetch(c - sm) : none();
+  CcRow<W, V> cur = fetch(c);
+  Vec<uint32_t, W> cd = ldv<W>(code, c);
+  Vec<A, W> ax = aux(c);
   for (int m = wk.m0; m < wk.m1; ++m, c += sm) {
     const bool more = m + 1 < wk.nm;  // uniform over the wave
     const bool own = m + 1 < wk.m1;   // the next row is this wave's too
-    const CcRow<V> nxt = more ? fetch(c + sm) : CcRow<V>{V(0), V(0)};
-    const uint32_t cdn = own ? code[c + sm] : 0u;
-    const A axn = own ? aux(c + sm) : A{};
-    V nb[8];
-    cc_neighbours(prev, cur, nxt, lane, nb);
+    const CcRow<W, V> nxt = more ? fetch(c + sm) : none();
+    Vec<uint32_t, W> cdn;
+    Vec<A, W> axn;
+    if (own) {
+      cdn = ldv<W>(code, c + sm);
+      axn = aux(c + sm);
+    }
+    V lp[W], rp[W], lc[W], rc[W], ln[W], rn[W];
+    cc_sides<W, V>(prev, lane, lp, rp);
+    cc_sides<W, V>(cur, lane, lc, rc);
+    cc_sides<W, V>(nxt, lane, ln, rn);
     // lanes past the grid only serve the shuffles
-    if (wk.act) store(c, body(c, cd, cur.v, nb, ax));
+    if (wk.act) {
+      Out o[W];
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        V nb[8];
+        nb[cc_dir(1, 0)] = rc[k];
+        nb[cc_dir(-1, 0)] = lc[k];
+        nb[cc_dir(0, 1)] = nxt.v.e[k];
+        nb[cc_dir(0, -1)] = prev.v.e[k];
+        nb[cc_dir(1, 1)] = rn[k];
+        nb[cc_dir(-1, 1)] = ln[k];
+        nb[cc_dir(1, -1)] = rp[k];
+        nb[cc_dir(-1, -1)] = lp[k];
+        o[k] = body(c + k, cd.e[k], cur.v.e[k], nb, ax.e[k]);
+      }
+      store(c, o);
+    }
     prev = cur;
     cur = nxt;
     cd = cdn;
@@ -1351,12 +1374,12 @@ __device__ inline void march_cc(const Walk &wk, Load load, Aux aux, Body body, S
 
 // P' = P + delta (the pending last CG step folded in as in k_outer),
 // r = S - (M - N) P' with (M - N) P' = sum_J a_J (P'_C - P'_J)
-template <typename T>
+template <typename T, int W>
 __global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const Inst *insts, State *sts,
                                                     double *part) {
   PI_PROLOGUE
   if (skip_outer(st)) return;
-  const Walk wk = make_walk<1>(in, e.lb);
+  const Walk wk = make_walk<W>(in, e.lb);
   const int cur = st->Pcur;
   const PI_G double *Pold = gp<double>(in.P[cur]);
   PI_G double *Pnew = gp<double>(in.P[cur ^ 1]);
@@ -1372,40 +1395,70 @@ __global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const 
   struct Out {
     double p, r;
   };
-  auto load = [&](int64_t q) { return Pold[q] + (double)(dl[q] + at * pt[q]); };
-  struct None {};
-  auto aux = [](int64_t) { return None{}; };
-  auto body = [&](int64_t c, uint32_t cd, double vC, const double (&nb)[8], None) -> Out {
+  struct Aux {
+    double S, d;
+  };
+  auto delta = [&](int64_t c) {
+    const Vec<T, W> d = ldv<W>(dl, c), p = ldv<W>(pt, c);
+    Vec<T, W> v;
+#pragma unroll
+    for (int k = 0; k < W; ++k) v.e[k] = d.e[k] + at * p.e[k];
+    return v;
+  };
+  auto load = [&](int64_t c) {
+    const Vec<double, W> P = ldv<W>(Pold, c);
+    const Vec<T, W> d = delta(c);
+    Vec<double, W> v;
+#pragma unroll
+    for (int k = 0; k < W; ++k) v.e[k] = P.e[k] + (double)d.e[k];
+    return v;
+  };
+  auto load1 = [&](int64_t c) -> double { return Pold[c] + (double)(dl[c] + at * pt[c]); };
+  auto aux = [&](int64_t c) {
+    const Vec<double, W> s = ldv<W>(S, c);
+    const Vec<T, W> d = delta(c);
+    Vec<Aux, W> x;
+#pragma unroll
+    for (int k = 0; k < W; ++k) x.e[k] = Aux{s.e[k], (double)d.e[k]};
+    return x;
+  };
+  auto body = [&](int64_t, uint32_t cd, double vC, const double (&nb)[8], const Aux &ax) -> Out {
     if (!(cd & kValidBit)) return Out{0.0, 0.0};
     double Lp = 0.0;
 #pragma unroll
     for (int j = 0; j < 8; ++j)
       if (cc_has(cd, j)) Lp += a[j] * (vC - nb[j]);
-    const double dC = (double)(dl[c] + at * pt[c]);
-    const double r = S[c] - Lp;
+    const double r = ax.S - Lp;
     const double rt = (double)(T)r;
     acc[0] += r * r;
     acc[1] += rt * rt;
-    acc[2] += dC * dC;
+    acc[2] += ax.d * ax.d;
     acc[3] += vC * vC;
     return Out{vC, r};
   };
-  auto store = [&](int64_t c, const Out &o) {
-    Pnew[c] = o.p;
-    res[c] = (T)o.r;
+  auto store = [&](int64_t c, const Out (&o)[W]) {
+    Vec<double, W> p;
+    Vec<T, W> r;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      p.e[k] = o[k].p;
+      r.e[k] = (T)o[k].r;
+    }
+    stv<W>(Pnew, c, p);
+    stv<W>(res, c, r);
   };
-  march_cc<double, None, Out>(wk, load, aux, body, store);
+  march_cc<W, double, Aux, Out>(wk, load, load1, aux, body, store);
   publish<4>(in, part, e.lb, acc);
 }
 
 // One inner CG iteration with the previous one's update folded in, as
 // k_cg_step, for the cell-centred scheme.
-template <typename T>
+template <typename T, int W>
 __global__ __launch_bounds__(kBlock) void k_cg_step_cc(const BlockEnt *tab, const Inst *insts, State *sts,
                                                       double *part) {
   PI_PROLOGUE
   if (skip_inner(in, st)) return;
-  const Walk wk = make_walk<1>(in, e.lb);
+  const Walk wk = make_walk<W>(in, e.lb);
   const CgPass<T> cg = cg_pass<T>(in, st);
   const bool opL = in.inner_op != 0;
   T a[8];
@@ -1415,14 +1468,26 @@ __global__ __launch_bounds__(kBlock) void k_cg_step_cc(const BlockEnt *tab, cons
   struct Out {
     T p, q, r, d;
   };
-  auto load = [&](int64_t o) { return (cg.rold[o] - cg.al * cg.qold[o]) + cg.be * cg.pold[o]; };
   struct Aux {
     T r, d;
   };
-  auto aux = [&](int64_t c) {
-    return Aux{cg.rold[c] - cg.al * cg.qold[c], (cg.rd_d ? cg.d[c] : T(0)) + cg.al * cg.pold[c]};
+  auto load = [&](int64_t c) {
+    const Vec<T, W> r = ldv<W>(cg.rold, c), q = ldv<W>(cg.qold, c), p = ldv<W>(cg.pold, c);
+    Vec<T, W> v;
+#pragma unroll
+    for (int k = 0; k < W; ++k) v.e[k] = (r.e[k] - cg.al * q.e[k]) + cg.be * p.e[k];
+    return v;
   };
-  auto body = [&](int64_t c, uint32_t cd, T pC, const T (&nb)[8], const Aux &ax) -> Out {
+  auto load1 = [&](int64_t o) -> T { return (cg.rold[o] - cg.al * cg.qold[o]) + cg.be * cg.pold[o]; };
+  auto aux = [&](int64_t c) {
+    const Vec<T, W> r = ldv<W>(cg.rold, c), q = ldv<W>(cg.qold, c), p = ldv<W>(cg.pold, c);
+    const Vec<T, W> d = cg.rd_d ? ldv<W>(cg.d, c) : vzero<T, W>();
+    Vec<Aux, W> x;
+#pragma unroll
+    for (int k = 0; k < W; ++k) x.e[k] = Aux{r.e[k] - cg.al * q.e[k], d.e[k] + cg.al * p.e[k]};
+    return x;
+  };
+  auto body = [&](int64_t, uint32_t cd, T pC, const T (&nb)[8], const Aux &ax) -> Out {
     if (!(cd & kValidBit)) return Out{T(0), T(0), T(0), T(0)};
     T s;
     if (opL) {
@@ -1442,26 +1507,33 @@ __global__ __launch_bounds__(kBlock) void k_cg_step_cc(const BlockEnt *tab, cons
       for (int j = 0; j < 8; ++j)
         if (cc_has(cd, j)) s -= (T)np1[j] * nb[j];
     }
-    const T rC = ax.r, dC = ax.d;
-    const double r = (double)rC, q = (double)s;
+    const double r = (double)ax.r, q = (double)s;
     acc[0] += (double)pC * q;
     acc[1] += r * q;
     acc[2] += q * q;
     acc[3] += r * r;
-    return Out{pC, s, rC, dC};
+    return Out{pC, s, ax.r, ax.d};
   };
-  auto store = [&](int64_t c, const Out &o) {
-    cg.pnew[c] = o.p;
-    cg.qnew[c] = o.q;
-    cg.rnew[c] = o.r;
-    if (cg.wr_d) cg.d[c] = o.d;
+  auto store = [&](int64_t c, const Out (&o)[W]) {
+    Vec<T, W> pv, qv, rv, dv;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      pv.e[k] = o[k].p;
+      qv.e[k] = o[k].q;
+      rv.e[k] = o[k].r;
+      dv.e[k] = o[k].d;
+    }
+    stv<W>(cg.pnew, c, pv);
+    stv<W>(cg.qnew, c, qv);
+    stv<W>(cg.rnew, c, rv);
+    if (cg.wr_d) stv<W>(cg.d, c, dv);
   };
-  march_cc<T, Aux, Out>(wk, load, aux, body, store);
+  march_cc<W, T, Aux, Out>(wk, load, load1, aux, body, store);
   publish<4>(in, part, e.lb, acc);
 }
 
 // y = M x, N x or (M - N) x for pi_apply
-template <typename T>
+template <typename T, int W>  // W: the plan's lane width; this kernel takes contiguous ranges
 __global__ __launch_bounds__(kBlock) void k_apply_cc(const BlockEnt *tab, const Inst *insts, State *sts,
                                                     double *part, int op, const T *x, T *y) {
   PI_PROLOGUE
@@ -1526,13 +1598,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_cc(const BlockEnt *tab, const 
 // ... and the cell-centred scheme has kernels of its own (KERN_cc)
 #define PI_MARCH(KERN, ...)                                                               \
   do {                                                                                    \
-    if (shape == kShapeCC) KERN##_cc<T><<<grid, block, 0, s>>>(__VA_ARGS__);              \
+    if (shape == kShapeCC) KERN##_cc<T, 1><<<grid, block, 0, s>>>(__VA_ARGS__);           \
+    else if (shape == kShapeCC4) KERN##_cc<T, 4><<<grid, block, 0, s>>>(__VA_ARGS__);     \
     else PI_MARCH8(KERN, __VA_ARGS__);                                                    \
   } while (0)
 
 template <typename T>
 static hipError_t launch_t(KernelId k, int shape, const LaunchArgs &la) {
-  const int ndim = (shape & 1) ? 3 : 2;
+  const int ndim = (shape == kShapeCC || shape == kShapeCC4) ? 2 : (shape & 1) ? 3 : 2;
   const dim3 grid(la.nblocks), block(kBlock);
   const BlockEnt *tab = la.tab;
   const Inst *insts = la.insts;
@@ -1542,18 +1615,18 @@ static hipError_t launch_t(KernelId k, int shape, const LaunchArgs &la) {
   switch (k) {
     case K_INIT: k_init<T><<<grid, block, 0, s>>>(PI_ARGS, la.iarg); break;
     case K_SOURCE:
-      if (shape == kShapeCC) k_source_cc<T><<<grid, block, 0, s>>>(PI_ARGS);
+      if (shape == kShapeCC || shape == kShapeCC4) k_source_cc<T><<<grid, block, 0, s>>>(PI_ARGS);
       else if (ndim == 3) k_source<T, 3><<<grid, block, 0, s>>>(PI_ARGS);
       else k_source<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
       break;
     case K_OUTER: PI_MARCH(k_outer, PI_ARGS); break;
     case K_CG_STEP: PI_MARCH(k_cg_step, PI_ARGS); break;
     case K_BICG_P:
-      if (shape == kShapeCC) return hipErrorInvalidValue;  // CG only
+      if (shape == kShapeCC || shape == kShapeCC4) return hipErrorInvalidValue;  // CG only
       PI_MARCH8(k_bicg_spmv_p, PI_ARGS);
       break;
     case K_BICG_S:
-      if (shape == kShapeCC) return hipErrorInvalidValue;
+      if (shape == kShapeCC || shape == kShapeCC4) return hipErrorInvalidValue;
       PI_MARCH8(k_bicg_spmv_s, PI_ARGS);
       break;
     case K_BICG_UPDATE: k_bicg_update<T><<<grid, block, 0, s>>>(PI_ARGS); break;

@@ -308,7 +308,7 @@ void set_walk(Inst &in, int ndim, const int64_t dims[3], int mseg_override, int 
   in.nz = ndim == 3 ? (int32_t)dims[2] : 1;
   in.ncell = (int64_t)in.nx * in.ny * in.nz;
   // four cells per lane (16-byte accesses) need rows that start 16-byte aligned
-  const bool can4 = in.nx % 4 == 0 && !in.cc;  // the cell-centred kernels take one cell per lane
+  const bool can4 = in.nx % 4 == 0;
   in.vw = vw_override == 1 ? 1 : (can4 ? 4 : 1);
   const int strip = kWave * in.vw;
   in.nxs = (in.nx + strip - 1) / strip;
@@ -670,7 +670,7 @@ extern "C" size_t pi_workspace_bytes(pi_plan_t p) { return p ? p->bytes : 0; }
 
 extern "C" pi_status pi_set_tile(pi_plan_t p, int32_t mseg, int32_t lane_cells) {
   if (!p || mseg < 0 || (lane_cells != 0 && lane_cells != 1 && lane_cells != 4)) return PI_ERR_INVALID_ARG;
-  if (lane_cells == 4 && (p->dims[0] % 4 != 0 || p->cc)) return PI_ERR_INVALID_ARG;
+  if (lane_cells == 4 && p->dims[0] % 4 != 0) return PI_ERR_INVALID_ARG;
   set_walk(p->inst, p->ndim, p->dims, mseg, lane_cells);
   if (plan_tables(p) != hipSuccess) return PI_ERR_OOM;
   if (hipMemcpy(p->d_inst, &p->inst, sizeof(Inst), hipMemcpyHostToDevice) != hipSuccess) return PI_ERR_DEVICE;

@@ -443,7 +443,7 @@ extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, v
   if (best[0] < 0) {
     std::vector<std::array<int32_t, 2>> cand;
     const std::vector<int32_t> widths =
-        p->dims[0] % 4 == 0 && !p->cc ? std::vector<int32_t>{4, 1} : std::vector<int32_t>{1};
+        p->dims[0] % 4 == 0 ? std::vector<int32_t>{4, 1} : std::vector<int32_t>{1};
     for (int32_t vw : widths) {
       if ((rc = pi_set_tile(p, 0, vw)) != PI_OK) return rc;
       cand.push_back({p->inst.mseg, vw});
