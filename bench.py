@@ -181,6 +181,29 @@ def timed_solve(plan, grads, P, tol, chunk, max_iter=10**7):
             return info
 
 
+def time_apply(pi, plan, reps, code_bytes):
+    """y = M x alone (pi_apply, the operator the CG pass applies), timed with
+    HIP events on the stream it is launched on.  Algorithmic bytes: x in,
+    y out (+ the 4-byte code where the plan reads it)."""
+    import torch
+
+    x = torch.randn(plan.shape, dtype=plan.dtype, device="cuda:0")
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    plan.apply(pi.PI_OP_M, x, y, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        plan.apply(pi.PI_OP_M, x, y, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ncell = x.numel()
+    alg = (2 * x.element_size() + code_bytes) * ncell
+    return {"op": "M = [W^{n+1}]", "avg_ms": ms, "launches": reps + 1, "alg_bytes": alg,
+            "achieved_GBs": alg / (ms * 1e-3) / 1e9, "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def kernel_mode(args, pi, plan, grads, P, ncell, bytes_per_cell=BYTES_PER_CELL):
     """Few dispatches: fill the workspace with four outer steps, then launch
     each outer-step kernel a few times, then run an element-wise int32 kernel
@@ -195,6 +218,7 @@ def kernel_mode(args, pi, plan, grads, P, ncell, bytes_per_cell=BYTES_PER_CELL):
         res[name] = {"avg_ms": ms, "launches": args.kernel_reps + 1,
                      "alg_bytes": bytes_per_cell[name] * ncell,
                      "achieved_GBs": bytes_per_cell[name] * ncell / (ms * 1e-3) / 1e9}
+    res["k_apply"] = time_apply(pi, plan, args.kernel_reps, bytes_per_cell["k_cg_step"] - 32)
     # yardstick with a kernel name nothing else here uses: reads and writes
     # 4 bytes per element
     x = torch.randint(0, 1 << 30, (ncell,), dtype=torch.int32, device="cuda:0")
@@ -631,6 +655,8 @@ def main():
     for name in kern:
         kern[name]["launches_per_solve"] = launches[name]
         kern[name]["share_of_solve"] = launches[name] * kern[name]["avg_ms"] * 1e-3 / sec
+    apply = time_apply(pi, plan, args.kernel_reps, bytes_per_cell["k_cg_step"] - 32)
+    progress(f"operator apply y = M x: {apply['avg_ms'] * 1e3:.1f} us, {apply['achieved_GBs']:.0f} GB/s")
     dom = max(kern, key=lambda k: kern[k]["launches_per_solve"] * kern[k]["avg_ms"])
     d = kern[dom]
     if cc:
@@ -674,6 +700,7 @@ def main():
         "autotune": tune,
         "roofline": roof,
         "kernels": kern,
+        "operator_apply": apply,
         "kernel_source_sha256": src_hash,
     }
     plan.close()

@@ -1140,6 +1140,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Ins
   __shared__ T lut_b[6][kStates];
   load_lut<T>(in.lut_np1, lut_a);
   load_lut<T>(in.lut_n, lut_b);
+  T wi[6];  // interior weights of [W^{n+1}], as the LUT holds them
+#pragma unroll
+  for (int d = 0; d < 6; ++d) wi[d] = (T)in.lut_np1[d][interior_state<ND>()];
   const Walk wk = make_walk<W>(in, e.lb);
   T a[6];
 #pragma unroll
@@ -1165,12 +1168,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Ins
       nb[DS] = vP;
     }
     T s;
-    if (op == 0) {  // M = I - W^{n+1}
-      s = vC;
-      for (int d = 0; d < 2 * ND; ++d) {
-        const int t = dstate(cd, d, bits);
-        if (t) s -= lut_a[d][t] * nb[d];
-      }
+    if (op == 0) {  // M = I - W^{n+1}, as the CG pass applies it
+      s = apply_m<T, ND>(lut_a, wi, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN);
     } else if (op == 1) {  // N = W^n with diagonal w_C^n
       T wc = T(1);
       s = T(0);
@@ -1182,12 +1181,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Ins
         }
       }
       s += wc * vC;
-    } else {  // M - N
-      s = T(0);
-      for (int d = 0; d < 2 * ND; ++d) {
-        const int t = dstate(cd, d, bits);
-        if (t) s += a[d] * (vC - nb[d]);
-      }
+    } else {  // M - N, as the variant's CG pass applies it
+      s = apply_l<T, ND>(a, cd, bits, vC, vW, vE, pl.vN, pl.vS, vP, vN);
     }
     return s;
   };
