@@ -165,3 +165,26 @@ def test_taylor_vortex_accuracy():
     t = gauge(sys_, sys_.from_grid(_np(P)))
     peak = np.abs(_np(P)).max()
     assert np.sqrt(np.mean((p - t) ** 2)) / peak < 2e-3
+
+
+def test_fixed_point_is_least_squares_in_the_group_constants():
+    """(M - N) has zero column sums, so a constant added to S over one group
+    has no solution; the oracle takes the least-squares answer, which is the
+    solution for S with that constant removed, and it spreads the residual
+    evenly over the group instead of leaving it in one pinned cell."""
+    m = np.ones((14, 17), np.uint8)
+    m[:, 8] = 0                                  # two groups
+    sys_ = assemble(m, (0.9, 1.2))
+    k, lab = components(sys_)
+    assert k == 2
+    rng = np.random.default_rng(4)
+    S = sys_.source([rng.normal(size=m.shape), rng.normal(size=m.shape)])
+    P = fixed_point(sys_, S)
+    shift = np.where(lab == 0, 1e-6, -3e-6)      # one constant per group
+    Q = fixed_point(sys_, S + shift)
+    assert np.abs(Q - P).max() < 1e-12 * np.abs(P).max()
+    r = S + shift - sys_.L @ Q
+    for c in range(k):
+        rc = r[lab == c]
+        assert np.abs(rc - rc.mean()).max() < 1e-12 * np.abs(S).max()
+        assert abs(rc.mean() - shift[lab == c][0]) < 1e-12
