@@ -155,3 +155,32 @@ def test_quadratic_pressure_is_recovered_exactly():
     got = np_(res.P)[s.valid]
     assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
     plan.close()
+
+
+def test_mixed_batch_of_schemes_and_shapes():
+    """One batched call over cell-centred plans (one and four cells per lane)
+    and face-crossing 2-D and 3-D plans: every instance matches its own
+    oracle's fixed point."""
+    import paper_2311_16935_amd as pi
+    from oracle.system import assemble
+
+    announce("cc mixed batch")
+    specs = [(synth.random_small(31, 2, (45, 37), mask_frac=0.1), True),
+             (synth.random_small(32, 2, (96, 45), mask_frac=0.1), True),
+             (synth.random_small(33, 2, (60, 41), mask_frac=0.1), False),
+             (synth.random_small(34, 3, (24, 17, 13), mask_frac=0.1), False)]
+    plans, grads, refs = [], [], []
+    for w, cc in specs:
+        mask = np.ones(tuple(reversed(w.dims)), np.uint8) if w.mask is None else np_(w.mask)
+        s = assemble_cc(mask, w.spacing) if cc else assemble(mask, w.spacing)
+        g = _grads(w, False)
+        plans.append(pi.Plan(w.dims, w.spacing, mask=w.mask, cell_centered=cc))
+        grads.append(g)
+        refs.append((s, fixed_point(s, s.source([np_(x).astype(np.float64) for x in g]))))
+    rc, Ps, infos = pi.solve_batched(plans, grads, tol=1e-10, max_iter=300000)
+    assert rc == 0, infos
+    for (s, ref), P, info in zip(refs, Ps, infos):
+        assert info["status"] == 0, info
+        assert rel_maxabs(np_(P).astype(np.float64)[s.valid], ref) <= 1e-5
+    for p in plans:
+        p.close()
