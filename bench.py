@@ -181,27 +181,49 @@ def timed_solve(plan, grads, P, tol, chunk, max_iter=10**7):
             return info
 
 
+APPLY_TILES = (4, 8, 16, 32)   # segment lengths (planes per wave) tried for pi_apply
+
+
 def time_apply(pi, plan, reps, code_bytes):
     """y = M x alone (pi_apply, the operator the CG pass applies), timed with
     HIP events on the stream it is launched on.  Algorithmic bytes: x in,
-    y out (+ the 4-byte code where the plan reads it)."""
+    y out (+ the 4-byte code where the plan reads it).
+
+    pi_apply runs at the plan's tile.  The solve's autotuner picks the tile
+    that balances its outer and CG kernels; the apply alone moves 8 bytes
+    per cell and needs more waves in flight, so it is timed at its own
+    segment length, picked from APPLY_TILES by a short sweep before the
+    timed launches.  The plan's tile is restored afterwards."""
     import torch
 
     x = torch.randn(plan.shape, dtype=plan.dtype, device="cuda:0")
     y = torch.empty_like(x)
     stream = torch.cuda.current_stream()
-    plan.apply(pi.PI_OP_M, x, y, stream=stream)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
+    keep = (pi.pi_get_tile(plan.handle), pi.pi_get_lane_cells(plan.handle))
+
+    def run(n):
         plan.apply(pi.PI_OP_M, x, y, stream=stream)
-    e1.record(stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            plan.apply(pi.PI_OP_M, x, y, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    sweep = {}
+    for mseg in APPLY_TILES:
+        pi.pi_set_tile(plan.handle, mseg, keep[1])
+        sweep[pi.pi_get_tile(plan.handle)] = run(3)
+    tile = min(sweep, key=sweep.get)
+    pi.pi_set_tile(plan.handle, tile, keep[1])
+    ms = run(reps)  # the last reps + 1 launches of k_apply run at this tile
+    pi.pi_set_tile(plan.handle, *keep)
     ncell = x.numel()
     alg = (2 * x.element_size() + code_bytes) * ncell
     return {"op": "M = [W^{n+1}]", "avg_ms": ms, "launches": reps + 1, "alg_bytes": alg,
-            "achieved_GBs": alg / (ms * 1e-3) / 1e9, "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "achieved_GBs": alg / (ms * 1e-3) / 1e9, "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "tile": tile, "lane_cells": keep[1], "tile_sweep_ms": {str(k): round(v, 5) for k, v in sweep.items()}}
 
 
 def kernel_mode(args, pi, plan, grads, P, ncell, bytes_per_cell=BYTES_PER_CELL):
@@ -656,7 +678,8 @@ def main():
         kern[name]["launches_per_solve"] = launches[name]
         kern[name]["share_of_solve"] = launches[name] * kern[name]["avg_ms"] * 1e-3 / sec
     apply = time_apply(pi, plan, args.kernel_reps, bytes_per_cell["k_cg_step"] - 32)
-    progress(f"operator apply y = M x: {apply['avg_ms'] * 1e3:.1f} us, {apply['achieved_GBs']:.0f} GB/s")
+    progress(f"operator apply y = M x: {apply['avg_ms'] * 1e3:.1f} us, {apply['achieved_GBs']:.0f} GB/s "
+             f"at {apply['tile']} planes per segment")
     dom = max(kern, key=lambda k: kern[k]["launches_per_solve"] * kern[k]["avg_ms"])
     d = kern[dom]
     if cc:

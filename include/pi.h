@@ -213,7 +213,10 @@ pi_status pi_source(pi_plan_t plan, const void *gx, const void *gy, const void *
  * plan's type; entries of x in masked cells are ignored, y is 0 there.
  * x and y must not overlap and must be 16-byte aligned when the plan moves
  * four cells per lane (pi_get_lane_cells == 4; torch allocations are), else
- * PI_ERR_INVALID_ARG.  Asynchronous.
+ * PI_ERR_INVALID_ARG.  Runs at the plan's current tile (pi_set_tile); the
+ * result does not depend on it, the speed does: the tile the solve's
+ * autotuner picks may give the apply too few waves, so a caller that applies
+ * often can set its own.  Asynchronous.
  */
 pi_status pi_apply(pi_plan_t plan, int op, const void *x, void *y, void *stream);
 

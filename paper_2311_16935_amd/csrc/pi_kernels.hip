@@ -306,6 +306,123 @@ __device__ inline void march(const Walk &wk, Load load, Load1 load1, Aux aux, Bo
   }
 }
 
+// The loads of one plane as issued, before anything is computed from them.
+template <typename LR, typename XR, typename L1R, int W>
+struct RawPlane {
+  LR v, vN, vS;
+  XR x;
+  L1R edge;
+  Vec<uint32_t, W> code;
+};
+
+// march with the loads of plane m + 2 in flight while plane m is computed.
+// march combines a plane's values as soon as they are loaded, so the wave
+// waits for every load it has just issued before it computes; here the
+// loaded values stay raw until their plane is consumed, and the copy of the
+// raw buffer at the end of an iteration is the only wait, after the plane's
+// arithmetic and stores have been issued.  It costs registers (the raw
+// inputs of one more plane), so kernels whose occupancy it would lower keep
+// march.
+//   load(c)  -> LR   raw operand inputs at cells c .. c+W-1
+//   load1(c) -> L1R  raw operand inputs at one cell (strip edges)
+//   extra(c) -> XR   raw extra per-cell input
+//   cookv(LR) -> Vec<V, W>, cook1(L1R) -> V, cooka(LR, XR) -> Vec<A, W>
+// Planes past the segment are loaded at a clamped, in-bounds position and
+// never used; the operand of the plane after the grid's last one reads 0.
+template <int ND, int W, bool GEN, typename V, typename A, typename Out, typename Load, typename Load1,
+          typename Extra, typename CookV, typename Cook1, typename CookA, typename Body, typename Store>
+__device__ inline void march2(const Walk &wk, Load load, Load1 load1, Extra extra, CookV cookv, Cook1 cook1,
+                              CookA cooka, Body body, Store store) {
+  if (wk.m1 <= wk.m0) return;  // uniform over the wave
+  const int lane = threadIdx.x & 63;
+  const bool hasN = ND == 3 && wk.row + 1 < wk.ny, hasS = ND == 3 && wk.row > 0;
+  const bool edgeW = lane == 0 && wk.x > 0, edgeE = lane == kWave - 1 && wk.x + W < wk.nx;
+  const int64_t snx = wk.nx;
+  const int64_t offN = hasN ? snx : 0, offS = hasS ? -snx : 0;
+  const int64_t offE = edgeW ? -1 : edgeE ? W : 0;
+  const bool hasEdge = edgeW || edgeE;
+  using LR = decltype(load(int64_t{}));
+  using XR = decltype(extra(int64_t{}));
+  using L1R = decltype(load1(int64_t{}));
+  using RP = RawPlane<LR, XR, L1R, W>;
+  const int jmax = min(wk.m1, wk.nm - 1);
+  const int64_t sm = wk.sm;
+  auto fetch = [&](int j, RP &rp) {
+    const int64_t cj = wk.base + (int64_t)min(j, jmax) * sm;
+    rp.v = load(cj);
+    if constexpr (!GEN) rp.code = ldv<W>(wk.code, cj);
+    rp.x = extra(cj);
+    if constexpr (ND == 3) {
+      rp.vN = load(cj + offN);
+      rp.vS = load(cj + offS);
+    }
+    rp.edge = load1(cj + offE);
+  };
+  auto cook = [&](int j, const RP &rp, Plane<V, A, W> &pl) {
+    const Vec<V, W> v = cookv(rp.v);
+    const bool in = j < wk.nm;
+#pragma unroll
+    for (int k = 0; k < W; ++k) pl.v.e[k] = in ? v.e[k] : V(0);
+    pl.aux = cooka(rp.v, rp.x);
+    if constexpr (GEN) {
+      const bool inner = j >= 2 && j + 2 < wk.nm && wk.x >= 2 && wk.x + W + 1 < wk.nx &&
+                         (ND == 2 || (wk.row >= 2 && wk.row + 2 < wk.ny));
+#pragma unroll
+      for (int k = 0; k < W; ++k)
+        pl.code.e[k] = inner ? interior_code<ND>()
+                             : (ND == 3 ? code_at<3>(wk.x + k, wk.row, j, wk.nx, wk.ny, wk.nz)
+                                        : code_at<2>(wk.x + k, j, 0, wk.nx, wk.ny, 1));
+    } else {
+      pl.code = rp.code;
+    }
+    if constexpr (ND == 3) {
+      const Vec<V, W> n = cookv(rp.vN), s = cookv(rp.vS);
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        pl.vN.e[k] = hasN ? n.e[k] : V(0);
+        pl.vS.e[k] = hasS ? s.e[k] : V(0);
+      }
+    }
+    const V e = cook1(rp.edge);
+    pl.vEdge = hasEdge ? e : V(0);
+  };
+  int64_t c = wk.base + (int64_t)wk.m0 * sm;
+  Vec<V, W> prev = vzero<V, W>();
+  if (wk.m0 > 0) prev = cookv(load(c - sm));
+  RP ra, rb;
+  fetch(wk.m0, ra);
+  fetch(wk.m0 + 1, rb);
+  Plane<V, A, W> cur, nxt;
+  cook(wk.m0, ra, cur);
+  for (int m = wk.m0; m < wk.m1; ++m, c += sm) {
+    fetch(m + 2, ra);
+    cook(m + 1, rb, nxt);
+    V left = __shfl_up(cur.v.e[W - 1], 1, kWave);
+    V right = __shfl_down(cur.v.e[0], 1, kWave);
+    if (lane == 0) left = cur.vEdge;
+    if (lane == kWave - 1) right = cur.vEdge;
+    if (wk.act) {
+      Out o[W];
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        const V vW = k == 0 ? left : cur.v.e[k > 0 ? k - 1 : 0];
+        const V vE = k == W - 1 ? right : cur.v.e[k + 1 < W ? k + 1 : 0];
+        Cell<V, A> cl;
+        cl.v = cur.v.e[k];
+        cl.vN = ND == 3 ? cur.vN.e[k] : V(0);
+        cl.vS = ND == 3 ? cur.vS.e[k] : V(0);
+        cl.aux = cur.aux.e[k];
+        cl.code = cur.code.e[k];
+        o[k] = body(c + k, cl, vW, vE, prev.e[k], nxt.v.e[k]);
+      }
+      store(c, o);
+    }
+    prev = cur.v;
+    cur = nxt;
+    rb = ra;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // point-wise work decomposition: block lb of an instance owns the cells
 // [lb * per, (lb + 1) * per) with per a multiple of 1024
@@ -1150,7 +1267,11 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Ins
   const int bits = dir_bits(ND);
   auto load = [&](int64_t c) { return ldv<W>(x, c); };
   auto load1 = [&](int64_t c) -> T { return x[c]; };
-  auto aux = [](int64_t) { return Vec<int, W>{}; };
+  struct None {};
+  auto extra = [](int64_t) { return None{}; };
+  auto cookv = [](const Vec<T, W> &v) { return v; };
+  auto cook1 = [](T v) { return v; };
+  auto cooka = [](const Vec<T, W> &, None) { return Vec<int, W>{}; };
   auto body = [&](int64_t, const Cell<T, int> &pl, T vW, T vE, T vP, T vN) -> T {
     const uint32_t cd = pl.code;
     const T vC = pl.v;
@@ -1192,7 +1313,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Ins
     for (int k = 0; k < W; ++k) v.e[k] = o[k];
     stv<W>(y, c, v);
   };
-  march<ND, W, GEN, T, int, T>(wk, load, load1, aux, body, store);
+  march2<ND, W, GEN, T, int, T>(wk, load, load1, extra, cookv, cook1, cooka, body, store);
 }
 
 

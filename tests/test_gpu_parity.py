@@ -332,6 +332,40 @@ def test_derived_codes_and_lane_widths_match_stored_codes(ndim, dims):
 FP_CASES = [fp64_cases()[0], fp64_cases()[2], fp64_cases()[4], fp32_cases()[1], fp32_cases()[3]]
 
 
+@pytest.mark.parametrize("ndim,dims,mask_frac", [(3, (36, 13, 11), 0.1), (3, (20, 9, 17), 0.0), (2, (44, 23), 0.1)])
+def test_apply_is_independent_of_segment_length(ndim, dims, mask_frac):
+    """The operator apply keeps loads of planes ahead in flight and walks
+    whole rounds of planes before a remainder; segment lengths from one plane
+    to the whole march axis (each remainder length, ragged last segments) and
+    both lane widths must give the same bits, equal to the oracle's product."""
+    import paper_2311_16935_amd as pi
+
+    announce("apply/segments", dims, mask_frac)
+    w = synth.random_small(61, ndim, dims, mask_frac=mask_frac)
+    sys_ = oracle_for(w)
+    plan = pi.Plan(w.dims, w.spacing, mask=w.mask)
+    rng = np.random.default_rng(7)
+    x = np.zeros(sys_.valid.shape)
+    x[sys_.valid] = rng.normal(size=sys_.n)
+    xt = torch.tensor(x, dtype=torch.float32, device=DEV)
+    xv = xt.cpu().double().numpy()[sys_.valid]
+    nm = dims[-1]
+    for op, mat in ((pi.PI_OP_M, sys_.M), (pi.PI_OP_N, sys_.N), (pi.PI_OP_L, sys_.L)):
+        ref = mat @ xv
+        first = None
+        for lanes in (1, 4):
+            for mseg in (1, 2, 3, 4, 5, 7, 8, nm):
+                pi.pi_set_tile(plan.handle, mseg, lanes)
+                y = plan.apply(op, xt).cpu()
+                if first is None:
+                    first = y
+                    yv = y.double().numpy()
+                    assert np.all(yv[~sys_.valid] == 0)
+                    assert np.abs(yv[sys_.valid] - ref).max() / np.abs(ref).max() < 2e-6, op
+                assert torch.equal(y, first), (op, lanes, mseg)
+    plan.close()
+
+
 @pytest.mark.parametrize("name,make", FP_CASES, ids=[c[0] for c in FP_CASES])
 @pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
 def test_fixed_point_cg_variant_reaches_the_same_field(name, make, fp64):
