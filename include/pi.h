@@ -146,6 +146,9 @@ pi_status pi_set_inner_iters(pi_plan_t plan, int32_t iters);
  * default.  lane_cells is 1 or 4 (4 needs nx % 4 == 0: each lane then moves
  * its cells with 16-byte accesses), 0 picks 4 when allowed, else 1.  The
  * autotuner sweeps both knobs.  Returns PI_ERR_INVALID_ARG for other values.
+ * Rebuilds the plan's block table (synchronous): PI_ERR_OOM if that fails,
+ * and then pi_solve, pi_source, pi_apply and pi_time_kernel on the plan
+ * return PI_ERR_OOM until a later pi_set_tile succeeds.
  * pi_get_tile / pi_get_lane_cells return the current values.
  */
 pi_status pi_set_tile(pi_plan_t plan, int32_t mseg, int32_t lane_cells);

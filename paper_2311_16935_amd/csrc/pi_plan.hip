@@ -431,13 +431,21 @@ hipError_t plan_tables(pi_plan_s *p) {
   if (p->d_part) (void)hipFree(p->d_part);
   p->d_tab = nullptr;
   p->d_part = nullptr;
+  p->ntab = 0;  // no table until the new one is in place
   std::vector<Inst *> one{&p->inst};
   int parts = 0;
   std::vector<BlockEnt> tab = build_table(one, 0, &parts);
-  p->ntab = (int)tab.size();
   hipError_t e = hipMalloc((void **)&p->d_tab, tab.size() * sizeof(BlockEnt));
   if (e == hipSuccess) e = hipMalloc((void **)&p->d_part, (size_t)std::max(parts, 1) * 4 * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(p->d_tab, tab.data(), tab.size() * sizeof(BlockEnt), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    p->ntab = (int)tab.size();
+  } else {
+    if (p->d_tab) (void)hipFree(p->d_tab);
+    if (p->d_part) (void)hipFree(p->d_part);
+    p->d_tab = nullptr;
+    p->d_part = nullptr;
+  }
   return e;
 }
 
@@ -671,12 +679,14 @@ extern "C" size_t pi_workspace_bytes(pi_plan_t p) { return p ? p->bytes : 0; }
 extern "C" pi_status pi_set_tile(pi_plan_t p, int32_t mseg, int32_t lane_cells) {
   if (!p || mseg < 0 || (lane_cells != 0 && lane_cells != 1 && lane_cells != 4)) return PI_ERR_INVALID_ARG;
   if (lane_cells == 4 && p->dims[0] % 4 != 0) return PI_ERR_INVALID_ARG;
-  set_walk(p->inst, p->ndim, p->dims, mseg, lane_cells);
-  if (plan_tables(p) != hipSuccess) return PI_ERR_OOM;
-  if (hipMemcpy(p->d_inst, &p->inst, sizeof(Inst), hipMemcpyHostToDevice) != hipSuccess) return PI_ERR_DEVICE;
+  // the captured outer-step graph holds the old table: drop it first, so
+  // that no failure below leaves it pointing at freed memory
   if (p->graph) (void)hipGraphExecDestroy(p->graph);
   p->graph = nullptr;
   p->graph_key = -1;
+  set_walk(p->inst, p->ndim, p->dims, mseg, lane_cells);
+  if (plan_tables(p) != hipSuccess) return PI_ERR_OOM;
+  if (hipMemcpy(p->d_inst, &p->inst, sizeof(Inst), hipMemcpyHostToDevice) != hipSuccess) return PI_ERR_DEVICE;
   return PI_OK;
 }
 

@@ -206,6 +206,10 @@ hipStream_t cap_stream(pi_plan_s *p) {
   return p->cap_stream;
 }
 
+// A plan whose pi_set_tile failed to allocate its block table has none
+// (ntab == 0): its calls report PI_ERR_OOM until a tile is set again.
+bool has_table(const pi_plan_s *p) { return p->ntab > 0 && p->d_tab && p->d_part; }
+
 Launcher single_launcher(pi_plan_s *p) {
   Launcher L;
   L.fp64 = p->fp64;
@@ -223,6 +227,7 @@ extern "C" pi_status pi_solve(pi_plan_t p, const void *gx, const void *gy, const
                               int64_t max_iter, uint32_t flags, pi_info *info, void *stream_) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!p || (flags & ~PI_WARM_START)) return PI_ERR_INVALID_ARG;
+  if (!has_table(p)) return PI_ERR_OOM;
   hipStream_t stream = (hipStream_t)stream_;
   Inst in = p->inst;
   if (!set_user(in, p, gx, gy, gz, P, tol, max_iter, flags)) return PI_ERR_INVALID_ARG;
@@ -350,6 +355,7 @@ done:
 
 extern "C" pi_status pi_source(pi_plan_t p, const void *gx, const void *gy, const void *gz, void *S, void *stream_) {
   if (!p || !gx || !gy || !S || (p->ndim == 3 && !gz)) return PI_ERR_INVALID_ARG;
+  if (!has_table(p)) return PI_ERR_OOM;
   hipStream_t stream = (hipStream_t)stream_;
   Inst in = p->inst;
   in.g[0] = gx;
@@ -371,6 +377,7 @@ extern "C" pi_status pi_apply(pi_plan_t p, int op, const void *x, void *y, void 
   if (!p || !x || !y || op < PI_OP_M || op > PI_OP_L || x == y) return PI_ERR_INVALID_ARG;
   // four cells per lane move 16-byte vectors
   if (p->inst.vw == 4 && (((uintptr_t)x | (uintptr_t)y) & 15u) != 0) return PI_ERR_INVALID_ARG;
+  if (!has_table(p)) return PI_ERR_OOM;
   hipStream_t stream = (hipStream_t)stream_;
   // the operator reads only plan fields of the device instance record, which
   // every call leaves in place
@@ -382,6 +389,7 @@ extern "C" pi_status pi_apply(pi_plan_t p, int op, const void *x, void *y, void 
 extern "C" pi_status pi_time_kernel(pi_plan_t p, int kernel, int32_t reps, double *avg_ms, void *stream_) {
   if (!p || !avg_ms || reps < 1 || (kernel != PI_K_OUTER && kernel != PI_K_INNER)) return PI_ERR_INVALID_ARG;
   if (kernel == PI_K_INNER && p->bicgstab) return PI_ERR_INVALID_ARG;
+  if (!has_table(p)) return PI_ERR_OOM;
   hipStream_t stream = (hipStream_t)stream_;
   const Launcher L = single_launcher(p);
   // a mid-solve state: a correction is pending, the search direction is not
