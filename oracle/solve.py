@@ -15,6 +15,13 @@ connected group of valid cells.  O2 solves it with one cell per group
 pinned (least squares in the rounding-level inconsistency), then applies the
 gauge.
 
+Route O2-CG -- the same fixed point for grids too large for a sparse LU:
+textbook conjugate gradients in FP64 on the assembled M - N.  The source is
+first projected onto the operator's range (its mean over every connected
+group removed, the least-squares reading of the rounding-level
+inconsistency described above), so the system is consistent and CG from 0
+stays in the range; the result is then gauged.
+
 Gauge: the paper fixes the free constant with one reference point (Sections
 on the PIV and SPIV examples).  Here the mean over every face-connected group
 of valid cells is removed instead, so that results can be compared cell by
@@ -132,3 +139,46 @@ def fixed_point(system: System, S) -> np.ndarray:
             P[keep] = lu.solve((S - lam[lab])[keep])
             lam = np.bincount(lab, weights=S - L @ P, minlength=k) / cnt
     return gauge(system, P)
+
+
+@dataclass
+class CgResult:
+    P: np.ndarray
+    iters: int
+    rel_residual: float      # ||b - L P|| / ||b||, recomputed from P at the end
+    converged: bool
+
+
+def fixed_point_cg(system: System, S, rtol: float = 1e-13, max_iter: int = 200000) -> CgResult:
+    """Route O2-CG: (M - N) P = S by plain conjugate gradients in FP64, gauged.
+
+    L = M - N is symmetric positive semi-definite with one zero eigenvalue per
+    connected group (the constants).  b = S minus its mean over each group
+    lies in L's range, so CG from P = 0 solves L P = b; the stopping test is
+    on the recursively updated residual, ||r|| <= rtol ||b||.  One sparse
+    product, two dot products and three vector updates per iteration, no
+    preconditioner."""
+    L = system.L.tocsr()
+    k, lab = components(system)
+    S = np.asarray(S, dtype=np.float64)
+    cnt = np.bincount(lab, minlength=k)
+    b = S - (np.bincount(lab, weights=S, minlength=k) / cnt)[lab]
+    nb = float(np.linalg.norm(b))
+    P = np.zeros(system.n)
+    if nb == 0.0:
+        return CgResult(gauge(system, P), 0, 0.0, True)
+    r = b.copy()
+    p = r.copy()
+    rr = float(r @ r)
+    it = 0
+    while it < max_iter and np.sqrt(rr) > rtol * nb:
+        q = L @ p
+        alpha = rr / float(p @ q)
+        P += alpha * p
+        r -= alpha * q
+        rr_new = float(r @ r)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        it += 1
+    rel = float(np.linalg.norm(b - L @ P) / nb)
+    return CgResult(gauge(system, P), it, rel, np.sqrt(rr) <= rtol * nb)

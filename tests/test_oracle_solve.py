@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import synth
-from oracle.solve import (components, fixed_point, gauge, outer_iteration,
+from oracle.solve import (components, fixed_point, fixed_point_cg, gauge, outer_iteration,
                           residual_momentum)
 from oracle.system import assemble
 
@@ -188,3 +188,81 @@ def test_fixed_point_is_least_squares_in_the_group_constants():
         rc = r[lab == c]
         assert np.abs(rc - rc.mean()).max() < 1e-12 * np.abs(S).max()
         assert abs(rc.mean() - shift[lab == c][0]) < 1e-12
+
+
+@pytest.mark.parametrize("dims,mask_frac,seed", [((29, 23), 0.15, 21), ((14, 11, 9), 0.12, 22),
+                                                 ((40, 9, 7), 0.0, 23)])
+def test_fixed_point_cg_matches_the_direct_route(dims, mask_frac, seed):
+    """Route O2-CG against route O2 (sparse LU with pinned cells): two
+    different algorithms for the same fixed point, on masked grids with
+    several groups, isolated cells and anisotropic spacing."""
+    w = synth.random_small(seed, len(dims), dims, mask_frac=mask_frac)
+    mask = np.ones(tuple(reversed(dims)), np.uint8) if w.mask is None else _np(w.mask)
+    sys_ = assemble(mask, w.spacing)
+    S = sys_.source([_np(x) for x in w.grads])
+    ref = fixed_point(sys_, S)
+    res = fixed_point_cg(sys_, S, rtol=1e-14)
+    assert res.converged and res.rel_residual < 1e-12
+    assert _rel_maxabs(res.P, ref) < 1e-11
+    k, lab = components(sys_)
+    for c in range(k):
+        assert abs(res.P[lab == c].mean()) < 1e-13 * np.abs(ref).max()
+
+
+def test_fixed_point_cg_exact_on_quadratic_fields():
+    P, g, sp = synth.quadratic((11, 9, 8), seed=6, spacing=(0.8, 1.3, 1.0))
+    mask = _disk_mask((11, 9, 8), 4, 0.12)
+    sys_ = assemble(mask, sp)
+    truth = gauge(sys_, sys_.from_grid(_np(P)))
+    res = fixed_point_cg(sys_, sys_.source([_np(x) for x in g]), rtol=1e-14)
+    assert _rel_maxabs(res.P, truth) < 1e-11
+
+
+def test_fixed_point_cg_ignores_group_constants_in_the_source():
+    # the projection onto the operator's range: a constant per group added to
+    # S changes nothing (the least-squares reading of route O2)
+    m = np.ones((12, 15), np.uint8)
+    m[:, 6] = 0
+    sys_ = assemble(m, (1.0, 0.7))
+    k, lab = components(sys_)
+    rng = np.random.default_rng(8)
+    S = sys_.source([rng.normal(size=m.shape), rng.normal(size=m.shape)])
+    a = fixed_point_cg(sys_, S, rtol=1e-14).P
+    b = fixed_point_cg(sys_, S + np.where(lab == 0, 2e-3, -5e-3), rtol=1e-14).P
+    assert np.abs(a - b).max() < 1e-11 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("dims,mask_frac", [((16, 13), 0.15), ((9, 8, 7), 0.1)])
+def test_one_outer_step_from_a_start_exact_where_w_n_reads(dims, mask_frac):
+    """Eq. MatrixEquation reads P^n only through [W^n], whose off-diagonal
+    w_j^n is non-zero only where a ray starts at J (a cell next to a missing
+    or out-of-grid cell) and whose diagonal w_C^n only where C itself has a
+    face without data.  So one exact outer step from any P^0 that equals the
+    fixed point on the cells [W^n] reads (its non-zero columns) lands on the
+    fixed point, whatever P^0 holds elsewhere, while an error on one of those
+    cells is carried on."""
+    w = synth.random_small(31, len(dims), dims, mask_frac=mask_frac)
+    sys_ = assemble(_np(w.mask), w.spacing)
+    S = sys_.source([_np(x) for x in w.grads])
+    star = fixed_point(sys_, S)
+    Nc = sys_.N.tocsc(copy=True)
+    Nc.eliminate_zeros()
+    read = np.diff(Nc.indptr) > 0
+    # the cells [W^n] reads are exactly those with a face neighbour without data
+    face_gap = np.zeros(sys_.n, bool)
+    for name, _, _ in __import__("oracle.counters", fromlist=["directions"]).directions(len(dims)):
+        r, _ = sys_.nbr[name]
+        has = np.zeros(sys_.n, bool)
+        has[r] = True
+        face_gap |= ~has
+    assert np.array_equal(read, face_gap)
+    assert 0 < read.sum() < sys_.n
+    rng = np.random.default_rng(3)
+    P0 = np.where(read, star + 0.75, rng.normal(size=sys_.n) * 10)
+    res = outer_iteration(sys_, S, tol=0.0, max_iter=1, P0=P0)
+    assert _rel_maxabs(gauge(sys_, res.P), star) < 1e-10
+    assert residual_momentum(sys_, S, res.P) < 1e-11
+    # one wrong value on a cell that [W^n] reads is not undone in one step
+    P0[np.flatnonzero(read)[read.sum() // 2]] += 1.0
+    res = outer_iteration(sys_, S, tol=0.0, max_iter=1, P0=P0)
+    assert residual_momentum(sys_, S, res.P) > 1e-6
