@@ -12,7 +12,14 @@ Prints one JSON line.  Besides the contract fields it carries
                 HIP events on the library's stream (pi_time_kernel)
   kernels       the same for the two kernels of an outer step
   cpu_baseline  the CPU FP64 oracle (route O1, sparse-LU inner solve) on a
-                bounded sample, scaled to one 256^3 solve
+                bounded sample, scaled to one 256^3 solve, and the oracle's
+                assembled-CSR operator apply timed at the benchmark size
+  oracle_check  the same recipe at 96^3 solved by the library and by the
+                oracle's route O2-CG: max-abs error over RMS(P) at the
+                benchmark tolerance and fully converged
+  fp64          one 256^3 solve in FP64 mode (the paper's precision)
+The side legs (warm start, variant, FP64) are deterministic and run one
+warm-up and at most SIDE_STEPS timed solves each.
 """
 
 from __future__ import annotations
@@ -41,6 +48,8 @@ BYTES_PER_CELL = {
 # the cell-centred kernels always read the 4-byte ring code of each cell
 BYTES_PER_CELL_CC = {k: v + 4 for k, v in BYTES_PER_CELL.items()}
 TIMED = (("k_outer", 0), ("k_cg_step", 1))  # names and pi_time_kernel ids (PI_K_OUTER, PI_K_INNER)
+SIDE_STEPS = 2        # timed solves of each side leg
+ORACLE_CHECK_N = 96   # side of the grid the oracle solves beside the library
 
 
 def parse():
@@ -83,6 +92,9 @@ def parse():
                     help="flow mode: report the source kernel only, without integrating the pressure")
     ap.add_argument("--no-variant", action="store_true",
                     help="skip the fixed-point CG variant (not the paper's iteration), reported beside it")
+    ap.add_argument("--no-oracle-check", action="store_true",
+                    help="skip the 96^3 same-recipe comparison with the oracle")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-mode solve")
     return ap.parse_args()
 
 
@@ -145,7 +157,9 @@ def cpu_baseline(n_sample, seed, n_target, tol, workload="blobs3d"):
     scale = (n_target / n_sample) ** (ndim + 1)
     return {
         "value": t * scale,
-        "unit": "s per %d^%d solve to eps_R<=%g (scaled)" % (n_target, ndim, tol),
+        "unit": "s per %d^%d solve to eps_R<=%g (extrapolated from the sample)" % (n_target, ndim, tol),
+        "extrapolated": True,
+        "scale_factor": scale,
         "cores": 1,
         "kind": "oracle",
         "sample": f"route O1 (exact sparse-LU inner solve) on {n_sample}^{ndim} {what}, seed {seed}: "
@@ -154,6 +168,94 @@ def cpu_baseline(n_sample, seed, n_target, tol, workload="blobs3d"):
         "sample_seconds": t,
         "sample_outer_iters": r.outer,
     }
+
+
+def cpu_spmv_at_size(n, seed, reps=3):
+    """The oracle's assembled operator M = [W^{n+1}] (CSR, FP64) applied to
+    a vector on the full benchmark grid, timed on one thread of this host:
+    the CPU counterpart of the library's operator apply.  Assembly (the
+    oracle's own, cell by cell in NumPy) is timed too but is set-up."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle.system import assemble
+
+    w = synth.config_blobs_3d(n, seed=seed)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        s = assemble(np.ones((n, n, n), np.uint8), w.spacing)
+        t_asm = time.perf_counter() - t0
+        M = s.M
+        x = np.random.default_rng(seed).standard_normal(s.n)
+        y = M @ x
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            y = M @ x
+        t = (time.perf_counter() - t0) / reps
+    del s, M, x, y
+    return {"n": n, "cells": n**3, "seconds_per_apply": t, "ns_per_cell": t / n**3 * 1e9,
+            "assembly_seconds": t_asm, "threads": 1, "reps": reps,
+            "what": "oracle CSR FP64 y = M x at the benchmark size (scipy sparse, single-threaded)"}
+
+
+def oracle_check(pi, n, seed, tol):
+    """The benchmark recipe at n^3 (same seed), solved by the library as the
+    benchmark runs it (FP32, autotuned tile) at the benchmark tolerance and
+    at 1e-10, against the oracle's FP64 fixed point (route O2-CG) of the same
+    FP32 gradient values."""
+    import numpy as np
+    import torch
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle.solve import fixed_point_cg
+    from oracle.system import assemble
+
+    w = synth.config_blobs_3d(n, seed=seed)
+    g32 = [x.to(torch.float32).contiguous() for x in w.grads]
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        s = assemble(np.ones((n, n, n), np.uint8), w.spacing)
+        S = s.source([x.numpy().astype(np.float64) for x in g32])
+        ref = fixed_point_cg(s, S, rtol=1e-14, max_iter=20000)
+        t_oracle = time.perf_counter() - t0
+    rms = float(np.sqrt(np.mean(ref.P**2)))
+    plan = pi.Plan(w.dims, w.spacing)
+    plan.autotune(reps=3)
+    g = [x.to("cuda:0") for x in g32]
+    out = {"n": n, "seed": seed, "recipe": "32 Gaussian blobs, 5 % noise (the benchmark's)",
+           "oracle": {"route": "O2-CG (FP64 CG on the fixed point, rtol 1e-14)", "iters": ref.iters,
+                      "rel_residual": ref.rel_residual, "seconds": t_oracle, "threads": 1}}
+    for key, t in (("at_tol", tol), ("converged", 1e-10)):
+        r = plan.solve(g, tol=t, max_iter=10**6)
+        P = r.P.cpu().numpy().astype(np.float64).ravel()
+        out[key] = {"tol": t, "status": r.status, "outer_iters": r.info["outer_iters"], "eps_R": r.info["eps_R"],
+                    "maxabs_rel_rms": float(np.abs(P - ref.P).max() / rms)}
+    plan.close()
+    out["bar_fp32"] = 1e-5
+    return out
+
+
+def fp64_leg(pi, grads, dims, spacing, tol):
+    """One solve in FP64 mode (the paper's precision): every vector, the
+    stencil and the updates in double."""
+    import torch
+
+    plan = pi.Plan(dims, spacing, fp64=True)
+    plan.autotune(reps=3)
+    g = [x.double() for x in grads]
+    P = torch.empty(plan.shape, dtype=torch.float64, device=g[0].device)
+    plan.solve(g, P=P, tol=tol, max_iter=8, check=False)   # captures the outer-step graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = plan.solve(g, P=P, tol=tol)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    plan.close()
+    del g, P
+    return {"s_per_solve": sec, "outer_iters": r.info["outer_iters"], "inner_iters": r.info["inner_iters_total"],
+            "eps_R": r.info["eps_R"], "status": r.status, "timed_solves": 1}
 
 
 def timed_solve(plan, grads, P, tol, chunk, max_iter=10**7):
@@ -267,13 +369,14 @@ def warm_start_leg(args, pi, plan, grads, P_plain, n):
     factor = n // int(net.meta.get("train_n", 64))
     ws = WarmStart(net, factor)
     P = torch.empty_like(P_plain)
-    for i in range(args.warmup):
+    steps = min(args.steps, SIDE_STEPS)
+    for i in range(min(args.warmup, 1)):
         r = ws.solve(plan, grads, P=P, tol=args.tol)
         progress(f"warm-start warmup {i}: {r.info['outer_iters']} outer steps")
     torch.cuda.synchronize()
     infos, t_guess = [], 0.0
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         a = time.perf_counter()
         ws.guess(plan, grads, P)
         torch.cuda.synchronize()
@@ -282,12 +385,13 @@ def warm_start_leg(args, pi, plan, grads, P_plain, n):
         infos.append(r.info)
         progress(f"warm-start step {i}: {r.info['outer_iters']} outer steps")
     torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / max(1, args.steps)
+    sec = (time.perf_counter() - t0) / max(1, steps)
     info = infos[-1]
     assert info["status"] == 0 and info["eps_R"] <= args.tol, info
     rms = float(P_plain.double().pow(2).mean().sqrt())
     diff = float((P.double() - P_plain.double()).abs().max()) / rms
-    return {"s_per_solve": sec, "guess_s": t_guess / max(1, args.steps), "outer_iters": info["outer_iters"],
+    return {"s_per_solve": sec, "timed_solves": steps, "guess_s": t_guess / max(1, steps),
+            "outer_iters": info["outer_iters"],
             "inner_iters": info["inner_iters_total"], "eps_R": info["eps_R"], "factor": factor,
             "weights": os.path.relpath(args.weights, ROOT), "train": {k: net.meta[k] for k in net.meta},
             "maxabs_vs_plain_rel_rms": diff}
@@ -304,16 +408,17 @@ def variant_leg(args, pi, grads, P_plain, dims, mask, spacing, weights_ok, cc=Fa
     n = dims[0]
     P = torch.empty_like(P_plain)
     out = {"inner_per_outer": None}
-    for i in range(args.warmup):
+    steps = min(args.steps, SIDE_STEPS)
+    for i in range(min(args.warmup, 1)):
         r = plan.solve(grads, P=P, tol=args.tol)
     rms = float(P_plain.double().pow(2).mean().sqrt()) if mask is None else \
         float(P_plain.double()[~P_plain.isnan()].pow(2).mean().sqrt())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         r = plan.solve(grads, P=P, tol=args.tol)
     torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / max(1, args.steps)
+    sec = (time.perf_counter() - t0) / max(1, steps)
     info = r.info
     assert info["status"] == 0 and info["eps_R"] <= args.tol, info
     diff = (P.double() - P_plain.double()).nan_to_num(0.0).abs().max()
@@ -329,10 +434,10 @@ def variant_leg(args, pi, grads, P_plain, dims, mask, spacing, weights_ok, cc=Fa
         ws.solve(plan, grads, P=P, tol=args.tol)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(args.steps):
+        for i in range(steps):
             r = ws.solve(plan, grads, P=P, tol=args.tol)
         torch.cuda.synchronize()
-        wsec = (time.perf_counter() - t0) / max(1, args.steps)
+        wsec = (time.perf_counter() - t0) / max(1, steps)
         out.update({"warm_s_per_solve": wsec, "warm_inner_iters": r.info["inner_iters_total"]})
         progress(f"fixed-point CG variant from the learned guess: {wsec:.3f} s per solve")
     plan.close()
@@ -664,6 +769,10 @@ def main():
     variant = None
     if not args.no_variant:
         variant = variant_leg(args, pi, grads, P_plain, dims, mask, w.spacing, weights_ok, cc)
+    fp64 = None
+    if not args.no_fp64 and args.workload == "blobs3d" and not args.chunk_outer_solve:
+        fp64 = fp64_leg(pi, grads, dims, w.spacing, args.tol)
+        progress(f"fp64 mode: {fp64['s_per_solve']:.2f} s, {fp64['outer_iters']} outer steps")
 
     # kernel durations, measured with HIP events on the library's stream
     src_hash = kernel_source_hash()
@@ -720,6 +829,7 @@ def main():
                   "inner_point_iters_per_s": ncell * info["inner_iters_total"] / sec},
         "warm_start": warm,
         "variant_fixed_point_cg": variant,
+        "fp64": fp64,
         "autotune": tune,
         "roofline": roof,
         "kernels": kern,
@@ -729,9 +839,19 @@ def main():
     plan.close()
     del grads, P
     torch.cuda.empty_cache()
+    if not args.no_oracle_check and args.workload == "blobs3d":
+        out["oracle_check"] = oracle_check(pi, ORACLE_CHECK_N, args.seed, args.tol)
+        progress(f"oracle check at {ORACLE_CHECK_N}^3: {out['oracle_check']['at_tol']['maxabs_rel_rms']:.2e} at "
+                 f"tol, {out['oracle_check']['converged']['maxabs_rel_rms']:.2e} converged")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_n if args.workload == "blobs3d" else 96, args.seed, n,
                                            args.tol, args.workload)
+        progress(f"cpu baseline sample: {out['cpu_baseline']['sample_seconds']:.1f} s")
+        if args.workload == "blobs3d":
+            out["cpu_baseline"]["at_size"] = cpu_spmv_at_size(n, args.seed)
+            if "oracle_check" in out:
+                out["cpu_baseline"]["at_size"]["o2_cg_solve"] = dict(out["oracle_check"]["oracle"], n=ORACLE_CHECK_N)
+            progress(f"cpu spmv at {n}^3: {out['cpu_baseline']['at_size']['seconds_per_apply']:.3f} s per apply")
     print(json.dumps(out), flush=True)
 
 

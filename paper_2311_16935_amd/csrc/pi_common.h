@@ -186,7 +186,9 @@ struct State {
                     // kernel does it)
   int32_t rcur;     // CG: current residual buffer (res / res1)
   int32_t qcur;     // CG: current M p buffer (q / q1)
-  int32_t pad;
+  int32_t dvalid;   // the correction buffer holds this outer step's sum: an
+                    // inner pass has written it since the outer step began
+                    // (the outer kernel reads it only then)
 };
 
 }  // namespace pi

@@ -619,6 +619,10 @@ __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Ins
   const T at = st->tail ? (T)st->alpha : T(0);
   const PI_G T *pt = gp<T>(in.p[st->pcur]);
   const PI_G T *dl = gp<T>(in.d);
+  // the correction buffer is read only once an inner pass of this outer step
+  // has written it: an inner solve that stops after its first pass leaves
+  // the previous outer step's sum there (uniform over the launch)
+  const bool use_d = st->dvalid != 0;
   const PI_G double *S = gp<double>(in.S64);
   PI_G T *res = gp<T>(st->rcur ? in.res1 : in.res);
   const int bits = dir_bits(ND);
@@ -634,7 +638,7 @@ __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Ins
   };
   // delta is zero before the first outer step (set when the solve starts)
   auto delta = [&](int64_t c) {
-    const Vec<T, W> d = ldv<W>(dl, c), p = ldv<W>(pt, c);
+    const Vec<T, W> d = use_d ? ldv<W>(dl, c) : vzero<T, W>(), p = ldv<W>(pt, c);
     Vec<T, W> v;
 #pragma unroll
     for (int k = 0; k < W; ++k) v.e[k] = d.e[k] + at * p.e[k];
@@ -648,7 +652,7 @@ __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Ins
     for (int k = 0; k < W; ++k) v.e[k] = P.e[k] + (double)d.e[k];
     return v;
   };
-  auto load1 = [&](int64_t c) -> double { return Pold[c] + (double)(dl[c] + at * pt[c]); };
+  auto load1 = [&](int64_t c) -> double { return Pold[c] + (double)((use_d ? dl[c] : T(0)) + at * pt[c]); };
   auto aux = [&](int64_t c) {
     const Vec<double, W> s = ldv<W>(S, c);
     const Vec<T, W> d = delta(c);
@@ -1185,6 +1189,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
         st->rr0 = s[1];
         st->inner = 0;
         st->tail = 0;
+        st->dvalid = 0;
         st->first = 1;
         st->beta = 0.0;  // the first search direction is the residual itself
         st->have_delta = 1;
@@ -1210,6 +1215,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
       st->tail = 1;  // alpha_k p_k is pending: the next pass or the outer kernel adds it
       st->inner += 1;
       st->inner_total += 1;
+      // every pass after the first writes the correction sum
+      if (st->inner >= 2) st->dvalid = 1;
       // fixed-point variant: the inner residual is the outer residual of
       // P + d, so the inner solve stops once it is well below the tolerance
       // (the FP64 outer step then confirms it), or once it is as small as
@@ -1233,6 +1240,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
       const double rho_new = s[0];
       st->beta = (st->rho != 0.0 && st->omega != 0.0) ? (rho_new / st->rho) * (st->alpha / st->omega) : 0.0;
       st->rho = rho_new;
+      st->dvalid = 1;  // every BiCGStab update writes the correction
       st->inner += 1;
       st->inner_total += 1;
       break;
@@ -1502,6 +1510,10 @@ __global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const 
   const T at = st->tail ? (T)st->alpha : T(0);
   const PI_G T *pt = gp<T>(in.p[st->pcur]);
   const PI_G T *dl = gp<T>(in.d);
+  // the correction buffer is read only once an inner pass of this outer step
+  // has written it: an inner solve that stops after its first pass leaves
+  // the previous outer step's sum there (uniform over the launch)
+  const bool use_d = st->dvalid != 0;
   const PI_G double *S = gp<double>(in.S64);
   PI_G T *res = gp<T>(st->rcur ? in.res1 : in.res);
   double a[8];
@@ -1515,7 +1527,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const 
     double S, d;
   };
   auto delta = [&](int64_t c) {
-    const Vec<T, W> d = ldv<W>(dl, c), p = ldv<W>(pt, c);
+    const Vec<T, W> d = use_d ? ldv<W>(dl, c) : vzero<T, W>(), p = ldv<W>(pt, c);
     Vec<T, W> v;
 #pragma unroll
     for (int k = 0; k < W; ++k) v.e[k] = d.e[k] + at * p.e[k];
@@ -1529,7 +1541,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const 
     for (int k = 0; k < W; ++k) v.e[k] = P.e[k] + (double)d.e[k];
     return v;
   };
-  auto load1 = [&](int64_t c) -> double { return Pold[c] + (double)(dl[c] + at * pt[c]); };
+  auto load1 = [&](int64_t c) -> double { return Pold[c] + (double)((use_d ? dl[c] : T(0)) + at * pt[c]); };
   auto aux = [&](int64_t c) {
     const Vec<double, W> s = ldv<W>(S, c);
     const Vec<T, W> d = delta(c);

@@ -403,6 +403,7 @@ extern "C" pi_status pi_time_kernel(pi_plan_t p, int kernel, int32_t reps, doubl
   st.have_delta = 1;
   st.tail = 1;
   st.inner = 2;  // a pass that reads and writes the correction
+  st.dvalid = 1;
   st.rr = 1.0;
   st.alpha = 1e-3;
   st.beta = 0.5;
