@@ -46,7 +46,8 @@ typedef enum pi_status {
   PI_ERR_NONFINITE = 3,     /* a data cell holds a NaN or infinite gradient    */
   PI_ERR_NOT_CONVERGED = 4, /* max_iter outer steps without reaching tol       */
   PI_ERR_DIVERGED = 5,      /* the residual became non-finite                  */
-  PI_ERR_DEVICE = 6         /* a HIP runtime call failed                       */
+  PI_ERR_DEVICE = 6,        /* a HIP runtime call failed                       */
+  PI_ERR_TOO_LARGE = 7      /* beyond pi_solve_batched_noalloc's fixed scratch */
 } pi_status;
 
 typedef struct pi_plan_s *pi_plan_t;
@@ -200,6 +201,34 @@ pi_status pi_solve_batched(int64_t count, const pi_plan_t *plans, const void *co
                            const void *const *gy, const void *const *gz, void *const *P,
                            const double *tol, int64_t max_iter, uint32_t flags, pi_info *infos,
                            void *stream);
+
+/*
+ * pi_solve_batched_noalloc -- pi_solve_batched for callers that cannot
+ * allocate device memory (tight serving loops, code under a capture or a
+ * harness that forbids hipMalloc): the same arguments, kernels and results,
+ * but the per-call device buffers (instance records, per-instance scalars,
+ * partial sums, block tables) live in one static device array of the
+ * library (about 15 MB on every GPU it runs on, held until the process
+ * ends: room for the limits below).  The call allocates no device or pinned host memory and
+ * creates no stream, event or graph: the outer steps are launched directly
+ * on `stream` and the convergence flags are copied back to pageable host
+ * memory every few outer steps (so it is slower per outer step than
+ * pi_solve_batched for small grids).  The plans still own their vectors.
+ * Limits: count <= PI_NOALLOC_MAX_INSTANCES, at most
+ * PI_NOALLOC_MAX_PARTIALS blocks over all instances and
+ * PI_NOALLOC_MAX_TABLE block-table entries; beyond them it returns
+ * PI_ERR_TOO_LARGE before touching the device.  Every call rewrites what the
+ * kernels read from the array before they run (it keeps the last call's
+ * contents).  Calls share one array per GPU; the library serialises them
+ * within a process, and returns once the work on `stream` has finished.
+ */
+#define PI_NOALLOC_MAX_INSTANCES 1024
+#define PI_NOALLOC_MAX_PARTIALS 262144
+#define PI_NOALLOC_MAX_TABLE 524288
+pi_status pi_solve_batched_noalloc(int64_t count, const pi_plan_t *plans, const void *const *gx,
+                                   const void *const *gy, const void *const *gz, void *const *P,
+                                   const double *tol, int64_t max_iter, uint32_t flags, pi_info *infos,
+                                   void *stream);
 
 /*
  * pi_source -- the source vector {S} (Eq. ExplicitEqn_FaceCrossing, last sum)

@@ -27,6 +27,10 @@ PI_ERR_NONFINITE = 3
 PI_ERR_NOT_CONVERGED = 4
 PI_ERR_DIVERGED = 5
 PI_ERR_DEVICE = 6
+PI_ERR_TOO_LARGE = 7
+PI_NOALLOC_MAX_INSTANCES = 1024
+PI_NOALLOC_MAX_PARTIALS = 262144
+PI_NOALLOC_MAX_TABLE = 524288
 
 PI_FP32 = 0x0
 PI_FP64 = 0x1
@@ -74,6 +78,8 @@ def _load():
                                      ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(dbl), i64, u32,
                                      ctypes.POINTER(PiInfo), vp]
     lib.pi_solve_batched.restype = ctypes.c_int
+    lib.pi_solve_batched_noalloc.argtypes = lib.pi_solve_batched.argtypes
+    lib.pi_solve_batched_noalloc.restype = ctypes.c_int
     lib.pi_source.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.pi_source.restype = ctypes.c_int
     lib.pi_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp]
@@ -97,7 +103,7 @@ lib = _load()
 
 EXPORTED = ("pi_plan", "pi_plan_destroy", "pi_workspace_bytes", "pi_set_inner_iters", "pi_set_tile",
             "pi_get_tile", "pi_get_lane_cells", "pi_solve",
-            "pi_solve_batched", "pi_source", "pi_apply", "pi_time_kernel", "pi_autotune", "pi_status_string")
+            "pi_solve_batched", "pi_solve_batched_noalloc", "pi_source", "pi_apply", "pi_time_kernel", "pi_autotune", "pi_status_string")
 
 PI_K_OUTER, PI_K_INNER = 0, 1
 
@@ -175,15 +181,22 @@ def pi_solve(plan, gx, gy, gz, P, tol, max_iter, flags=0, stream=None):
     return rc, info
 
 
-def pi_solve_batched(plans, gx, gy, gz, P, tol, max_iter, flags=0, stream=None):
+def _batched(fn, plans, gx, gy, gz, P, tol, max_iter, flags, stream):
     n = len(plans)
     vp = ctypes.c_void_p
     arr = lambda xs: (vp * n)(*[None if x is None else x.data_ptr() for x in xs])  # noqa: E731
     infos = (PiInfo * n)()
-    rc = lib.pi_solve_batched(n, (vp * n)(*[p.value for p in plans]), arr(gx), arr(gy),
-                              arr(gz) if gz is not None else None, arr(P), (ctypes.c_double * n)(*tol),
-                              int(max_iter), ctypes.c_uint32(flags), infos, _stream(stream))
+    rc = fn(n, (vp * n)(*[p.value for p in plans]), arr(gx), arr(gy), arr(gz) if gz is not None else None, arr(P),
+            (ctypes.c_double * n)(*tol), int(max_iter), ctypes.c_uint32(flags), infos, _stream(stream))
     return rc, list(infos)
+
+
+def pi_solve_batched(plans, gx, gy, gz, P, tol, max_iter, flags=0, stream=None):
+    return _batched(lib.pi_solve_batched, plans, gx, gy, gz, P, tol, max_iter, flags, stream)
+
+
+def pi_solve_batched_noalloc(plans, gx, gy, gz, P, tol, max_iter, flags=0, stream=None):
+    return _batched(lib.pi_solve_batched_noalloc, plans, gx, gy, gz, P, tol, max_iter, flags, stream)
 
 
 def pi_source(plan, gx, gy, gz, S, stream=None) -> int:
@@ -309,8 +322,9 @@ class Plan:
 
 
 def solve_batched(plans, grads_list, P_list=None, tol=1e-6, max_iter=10**7, warm_start=False, stream=None,
-                  check=True):
-    """One batched solve over ``plans`` (all of one precision)."""
+                  check=True, noalloc=False):
+    """One batched solve over ``plans`` (all of one precision); with
+    ``noalloc`` through pi_solve_batched_noalloc (no device allocation)."""
     n = len(plans)
     if P_list is None:
         P_list = [torch.empty(p.shape, dtype=p.dtype, device=g[0].device) for p, g in zip(plans, grads_list)]
@@ -320,9 +334,9 @@ def solve_batched(plans, grads_list, P_list=None, tol=1e-6, max_iter=10**7, warm
         p._check(P, "P")
     tols = [float(tol)] * n if not isinstance(tol, (list, tuple)) else [float(t) for t in tol]
     gz = [g[2] if p.ndim == 3 else None for p, g in zip(plans, grads_list)]
-    rc, infos = pi_solve_batched([p.handle for p in plans], [g[0] for g in grads_list],
-                                 [g[1] for g in grads_list], gz, P_list, tols, max_iter,
-                                 PI_WARM_START if warm_start else 0, stream)
+    fn = pi_solve_batched_noalloc if noalloc else pi_solve_batched
+    rc, infos = fn([p.handle for p in plans], [g[0] for g in grads_list], [g[1] for g in grads_list], gz, P_list,
+                   tols, max_iter, PI_WARM_START if warm_start else 0, stream)
     if check and rc not in (PI_OK, PI_ERR_NOT_CONVERGED):
-        raise PiError(rc, "pi_solve_batched")
+        raise PiError(rc, fn.__name__)
     return rc, P_list, [i.as_dict() for i in infos]

@@ -254,92 +254,117 @@ extern "C" pi_status pi_solve(pi_plan_t p, const void *gx, const void *gy, const
   return (pi_status)p->h_state->status;
 }
 
+namespace {
+
+// Host side of a batched call: validated instance records, and the block
+// table of each launch shape with partial slots numbered across all.
+struct BatchSetup {
+  bool fp64 = false;
+  bool bicg = false;
+  int inner = 1;
+  int parts = 0;
+  std::vector<Inst> host;
+  std::vector<BlockEnt> tabs[kShapes];
+};
+
+pi_status batch_setup(int64_t count, const pi_plan_t *plans, const void *const *gx, const void *const *gy,
+                      const void *const *gz, void *const *P, const double *tol, int64_t max_iter, uint32_t flags,
+                      BatchSetup &b) {
+  if (count < 1 || !plans || !gx || !gy || !P || !tol || (flags & ~PI_WARM_START)) return PI_ERR_INVALID_ARG;
+  b.fp64 = plans[0] ? plans[0]->fp64 : false;
+  b.bicg = plans[0] ? plans[0]->bicgstab : false;
+  b.host.resize(count);
+  for (int64_t i = 0; i < count; ++i) {
+    pi_plan_s *p = plans[i];
+    if (!p || p->fp64 != b.fp64 || p->bicgstab != b.bicg) return PI_ERR_INVALID_ARG;
+    for (int64_t j = 0; j < i; ++j)
+      if (plans[j] == p) return PI_ERR_INVALID_ARG;
+    b.host[i] = p->inst;
+    if (!set_user(b.host[i], p, gx[i], gy[i], gz ? gz[i] : nullptr, P[i], tol[i], max_iter, flags))
+      return PI_ERR_INVALID_ARG;
+    b.inner = std::max(b.inner, p->inner_iters);
+  }
+  std::vector<Inst *> by[kShapes];
+  std::vector<int64_t> idx[kShapes];
+  for (int64_t i = 0; i < count; ++i) {
+    const Inst &h = b.host[i];
+    const int g = shape_of(h.ndim, h.vw, h.gen, h.cc);
+    by[g].push_back(&b.host[i]);
+    idx[g].push_back(i);
+  }
+  b.parts = 0;
+  for (int g = 0; g < kShapes; ++g) {
+    if (by[g].empty()) continue;
+    int total = 0;
+    b.tabs[g] = build_table(by[g], b.parts, &total);
+    // the table names instances by position inside the group; map to batch index
+    for (auto &e : b.tabs[g])
+      if (e.inst >= 0) e.inst = (int32_t)idx[g][e.inst];
+    b.parts = total;
+  }
+  return PI_OK;
+}
+
+pi_status batch_report(int64_t count, const pi_plan_t *plans, const State *hst, pi_info *infos,
+                       std::chrono::steady_clock::time_point t0) {
+  const double ms = ms_since(t0);
+  int w = PI_OK;
+  for (int64_t i = 0; i < count; ++i) {
+    fill_info(infos ? infos + i : nullptr, hst[i], plans[i], ms);
+    w = worst(w, hst[i].status);
+  }
+  return (pi_status)w;
+}
+
+}  // namespace
+
 extern "C" pi_status pi_solve_batched(int64_t count, const pi_plan_t *plans, const void *const *gx,
                                       const void *const *gy, const void *const *gz, void *const *P,
                                       const double *tol, int64_t max_iter, uint32_t flags, pi_info *infos,
                                       void *stream_) {
   const auto t0 = std::chrono::steady_clock::now();
-  if (count < 1 || !plans || !gx || !gy || !P || !tol || (flags & ~PI_WARM_START)) return PI_ERR_INVALID_ARG;
+  BatchSetup b;
+  pi_status rc = batch_setup(count, plans, gx, gy, gz, P, tol, max_iter, flags, b);
+  if (rc != PI_OK) return rc;
   hipStream_t stream = (hipStream_t)stream_;
-  const bool fp64 = plans[0] ? plans[0]->fp64 : false;
-  const bool bicg = plans[0] ? plans[0]->bicgstab : false;
-  int inner = 1;
-  std::vector<Inst> host(count);
-  for (int64_t i = 0; i < count; ++i) {
-    pi_plan_s *p = plans[i];
-    if (!p || p->fp64 != fp64 || p->bicgstab != bicg) return PI_ERR_INVALID_ARG;
-    for (int64_t j = 0; j < i; ++j)
-      if (plans[j] == p) return PI_ERR_INVALID_ARG;
-    host[i] = p->inst;
-    if (!set_user(host[i], p, gx[i], gy[i], gz ? gz[i] : nullptr, P[i], tol[i], max_iter, flags))
-      return PI_ERR_INVALID_ARG;
-    inner = std::max(inner, p->inner_iters);
-  }
-  // block tables per launch shape; partial slots are numbered across all
-  std::vector<Inst *> by[kShapes];
-  std::vector<int64_t> idx[kShapes];
-  for (int64_t i = 0; i < count; ++i) {
-    const int g = shape_of(host[i].ndim, host[i].vw, host[i].gen, host[i].cc);
-    by[g].push_back(&host[i]);
-    idx[g].push_back(i);
-  }
-  std::vector<BlockEnt> tabs[kShapes];
-  int parts = 0;
-  for (int g = 0; g < kShapes; ++g) {
-    if (by[g].empty()) continue;
-    int total = 0;
-    tabs[g] = build_table(by[g], parts, &total);
-    // the table names instances by position inside the group; map to batch index
-    for (auto &e : tabs[g])
-      if (e.inst >= 0) e.inst = (int32_t)idx[g][e.inst];
-    parts = total;
-  }
   Launcher L;
-  L.fp64 = fp64;
+  L.fp64 = b.fp64;
   L.count = (int)count;
   hipStream_t cap = nullptr;
   hipGraphExec_t exec = nullptr;
   State *hst = nullptr;
-  pi_status rc = PI_ERR_DEVICE;
+  rc = PI_ERR_DEVICE;
   std::vector<State> init(count, fresh_state());
   if (hipMalloc((void **)&L.insts, count * sizeof(Inst)) != hipSuccess ||
       hipMalloc((void **)&L.sts, count * sizeof(State)) != hipSuccess ||
-      hipMalloc((void **)&L.part, (size_t)std::max(parts, 1) * 4 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void **)&L.part, (size_t)std::max(b.parts, 1) * 4 * sizeof(double)) != hipSuccess ||
       hipHostMalloc((void **)&hst, 2 * count * sizeof(State), hipHostMallocDefault) != hipSuccess) {
     rc = PI_ERR_OOM;
     goto done;
   }
   for (int g = 0; g < kShapes; ++g) {
-    if (tabs[g].empty()) continue;
-    if (hipMalloc((void **)&L.grp[g].tab, tabs[g].size() * sizeof(BlockEnt)) != hipSuccess) {
+    if (b.tabs[g].empty()) continue;
+    if (hipMalloc((void **)&L.grp[g].tab, b.tabs[g].size() * sizeof(BlockEnt)) != hipSuccess) {
       rc = PI_ERR_OOM;
       goto done;
     }
-    L.grp[g].ntab = (int)tabs[g].size();
-    if (hipMemcpyAsync(L.grp[g].tab, tabs[g].data(), tabs[g].size() * sizeof(BlockEnt), hipMemcpyHostToDevice,
+    L.grp[g].ntab = (int)b.tabs[g].size();
+    if (hipMemcpyAsync(L.grp[g].tab, b.tabs[g].data(), b.tabs[g].size() * sizeof(BlockEnt), hipMemcpyHostToDevice,
                        stream) != hipSuccess)
       goto done;
   }
-  if (hipMemcpyAsync(L.insts, host.data(), count * sizeof(Inst), hipMemcpyHostToDevice, stream) != hipSuccess ||
+  if (hipMemcpyAsync(L.insts, b.host.data(), count * sizeof(Inst), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemcpyAsync(L.sts, init.data(), count * sizeof(State), hipMemcpyHostToDevice, stream) != hipSuccess)
     goto done;
   if (L.go(K_INIT, stream, (flags & PI_WARM_START) ? 1 : 0) != hipSuccess || L.go(K_SOURCE, stream) != hipSuccess)
     goto done;
   if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) goto done;
-  if (capture(L, cap, inner, bicg, &exec) != hipSuccess) goto done;
-  rc = iterate(exec, stream, L.sts, hst, count, max_iter, unroll_for(inner));
+  if (capture(L, cap, b.inner, b.bicg, &exec) != hipSuccess) goto done;
+  rc = iterate(exec, stream, L.sts, hst, count, max_iter, unroll_for(b.inner));
   if (rc != PI_OK) goto done;
   rc = finish(L, stream, L.sts, hst, count);
   if (rc != PI_OK) goto done;
-  {
-    const double ms = ms_since(t0);
-    int w = PI_OK;
-    for (int64_t i = 0; i < count; ++i) {
-      fill_info(infos ? infos + i : nullptr, hst[i], plans[i], ms);
-      w = worst(w, hst[i].status);
-    }
-    rc = (pi_status)w;
-  }
+  rc = batch_report(count, plans, hst, infos, t0);
 done:
   if (exec) (void)hipGraphExecDestroy(exec);
   if (cap) (void)hipStreamDestroy(cap);
@@ -350,6 +375,126 @@ done:
   for (int g = 0; g < kShapes; ++g)
     if (L.grp[g].tab) (void)hipFree(L.grp[g].tab);
   if (hst) (void)hipHostFree(hst);
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// pi_solve_batched_noalloc: the batched solve with its per-call device
+// buffers (instance records, scalars, partial sums, block tables) carved
+// out of one static device array instead of allocated
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kNaInsts = PI_NOALLOC_MAX_INSTANCES;
+constexpr int64_t kNaParts = PI_NOALLOC_MAX_PARTIALS;
+constexpr int64_t kNaTab = PI_NOALLOC_MAX_TABLE;
+
+constexpr size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+constexpr size_t kNaOffSts = align256(kNaInsts * sizeof(Inst));
+constexpr size_t kNaOffPart = kNaOffSts + align256(kNaInsts * sizeof(State));
+constexpr size_t kNaOffTab = kNaOffPart + align256(kNaParts * 4 * sizeof(double));
+constexpr size_t kNaBytes = kNaOffTab + align256(kNaTab * sizeof(BlockEnt));
+
+}  // namespace
+
+// One per GPU the library runs on, held until the process ends.  Host code
+// never passes this name to a kernel or a copy: it is a host-side stand-in;
+// the device address comes from hipGetSymbolAddress (noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_na_mu;
+unsigned char *g_na_ptr[kMaxDevices] = {};
+State g_na_host[2 * kNaInsts];  // polling snapshots (pageable host memory)
+
+// Device address of this GPU's scratch array, looked up once per device
+// with that device current.
+hipError_t noalloc_scratch(unsigned char **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_na_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_na_ptr[dev] = (unsigned char *)ptr;
+  }
+  *out = g_na_ptr[dev];
+  return hipSuccess;
+}
+
+// Replays of the outer-step sequence without a graph: the launches go
+// straight onto the stream; the done flags are copied back to pageable host
+// memory and checked every `unroll` outer steps.
+pi_status noalloc_iterate(const Launcher &L, hipStream_t stream, int64_t count, int64_t max_iter, int inner,
+                          bool bicg) {
+  const int unroll = unroll_for(inner);
+  const int64_t bound = max_iter / unroll + 4;
+  const size_t bytes = (size_t)count * sizeof(State);
+  for (int64_t r = 0; r < bound; ++r) {
+    if (L.outer_steps(stream, unroll, inner, bicg) != hipSuccess) return PI_ERR_DEVICE;
+    if (hipMemcpyAsync(g_na_host, L.sts, bytes, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return PI_ERR_DEVICE;
+    bool all = true;
+    for (int64_t i = 0; i < count && all; ++i) all = g_na_host[i].done != 0;
+    if (all) return PI_OK;
+  }
+  return PI_ERR_DEVICE;
+}
+
+}  // namespace
+
+extern "C" pi_status pi_solve_batched_noalloc(int64_t count, const pi_plan_t *plans, const void *const *gx,
+                                              const void *const *gy, const void *const *gz, void *const *P,
+                                              const double *tol, int64_t max_iter, uint32_t flags, pi_info *infos,
+                                              void *stream_) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (count > kNaInsts) return PI_ERR_TOO_LARGE;
+  BatchSetup b;
+  pi_status rc = batch_setup(count, plans, gx, gy, gz, P, tol, max_iter, flags, b);
+  if (rc != PI_OK) return rc;
+  int64_t ntab = 0;
+  for (int g = 0; g < kShapes; ++g) ntab += (int64_t)b.tabs[g].size();
+  if (b.parts > kNaParts || ntab > kNaTab) return PI_ERR_TOO_LARGE;
+  // one caller at a time: the scratch array and the host snapshots are shared
+  std::lock_guard<std::mutex> guard(g_na_mu);
+  unsigned char *base = nullptr;
+  if (noalloc_scratch(&base) != hipSuccess) return PI_ERR_DEVICE;
+  hipStream_t stream = (hipStream_t)stream_;
+  Launcher L;
+  L.fp64 = b.fp64;
+  L.count = (int)count;
+  L.insts = (Inst *)(base);
+  L.sts = (State *)(base + kNaOffSts);
+  L.part = (double *)(base + kNaOffPart);
+  BlockEnt *tab = (BlockEnt *)(base + kNaOffTab);
+  for (int g = 0; g < kShapes; ++g) {
+    if (b.tabs[g].empty()) continue;
+    L.grp[g].tab = tab;
+    L.grp[g].ntab = (int)b.tabs[g].size();
+    if (hipMemcpyAsync(tab, b.tabs[g].data(), b.tabs[g].size() * sizeof(BlockEnt), hipMemcpyHostToDevice,
+                       stream) != hipSuccess)
+      return PI_ERR_DEVICE;
+    tab += b.tabs[g].size();
+  }
+  // every record and scalar the kernels read is written here first: the
+  // array keeps the previous call's contents
+  for (int64_t i = 0; i < count; ++i) g_na_host[i] = fresh_state();
+  if (hipMemcpyAsync(L.insts, b.host.data(), count * sizeof(Inst), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(L.sts, g_na_host, count * sizeof(State), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return PI_ERR_DEVICE;
+  if (L.go(K_INIT, stream, (flags & PI_WARM_START) ? 1 : 0) != hipSuccess || L.go(K_SOURCE, stream) != hipSuccess)
+    return PI_ERR_DEVICE;
+  rc = noalloc_iterate(L, stream, count, max_iter, b.inner, b.bicg);
+  if (rc == PI_OK) rc = finish(L, stream, L.sts, g_na_host, count);
+  if (rc == PI_OK) rc = batch_report(count, plans, g_na_host, infos, t0);
+  (void)hipStreamSynchronize(stream);
   return rc;
 }
 
@@ -489,6 +634,7 @@ extern "C" const char *pi_status_string(pi_status s) {
     case PI_ERR_NOT_CONVERGED: return "not converged within max_iter outer steps";
     case PI_ERR_DIVERGED: return "residual became non-finite";
     case PI_ERR_DEVICE: return "HIP runtime error";
+    case PI_ERR_TOO_LARGE: return "exceeds the fixed scratch size of the no-allocation entry point";
   }
   return "unknown status";
 }

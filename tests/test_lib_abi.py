@@ -90,3 +90,14 @@ def test_cell_centered_flag_checks_fail_before_touching_the_device():
         with pytest.raises(pi.PiError) as e:
             pi.pi_plan(*args)
         assert e.value.status == pi.PI_ERR_INVALID_ARG
+
+
+def test_noalloc_size_limit_fails_before_touching_the_device():
+    import ctypes
+
+    import paper_2311_16935_amd as pi
+
+    n = pi.PI_NOALLOC_MAX_INSTANCES + 1
+    rc = pi.lib.pi_solve_batched_noalloc(n, None, None, None, None, None, None, 10, ctypes.c_uint32(0), None, None)
+    assert rc == pi.PI_ERR_TOO_LARGE
+    assert "scratch" in pi.pi_status_string(rc)
