@@ -356,23 +356,19 @@ def kernel_mode(args, pi, plan, grads, P, ncell, bytes_per_cell=BYTES_PER_CELL):
                       "kernels": res, "kernel_source_sha256": kernel_source_hash()}), flush=True)
 
 
-def warm_start_leg(args, pi, plan, grads, P_plain, n):
-    """The same solve from the learned guess: inference (gradient RMS, 4x
-    block means, U-Net, trilinear upsampling) plus the plain solver finishing
-    from the guess, timed end to end per solve; the converged field is
-    compared with the zero-start answer."""
+def warm_start_leg(args, pi, plan, grads, P_plain, n, ws, label):
+    """The same solve from a warm start: the guess (network inference --
+    gradient RMS, block means, U-Net -- and/or the coarse solve, then
+    trilinear upsampling) plus the plain solver finishing from it, timed end
+    to end per solve; the converged field is compared with the zero-start
+    answer."""
     import torch
 
-    from paper_2311_16935_amd.warmstart import UNet, WarmStart
-
-    net = UNet.from_file(args.weights)
-    factor = n // int(net.meta.get("train_n", 64))
-    ws = WarmStart(net, factor)
     P = torch.empty_like(P_plain)
     steps = min(args.steps, SIDE_STEPS)
     for i in range(min(args.warmup, 1)):
         r = ws.solve(plan, grads, P=P, tol=args.tol)
-        progress(f"warm-start warmup {i}: {r.info['outer_iters']} outer steps")
+        progress(f"{label} warmup {i}: {r.info['outer_iters']} outer steps")
     torch.cuda.synchronize()
     infos, t_guess = [], 0.0
     t0 = time.perf_counter()
@@ -383,18 +379,42 @@ def warm_start_leg(args, pi, plan, grads, P_plain, n):
         t_guess += time.perf_counter() - a
         r = plan.solve(grads, P=P, tol=args.tol, warm_start=True)
         infos.append(r.info)
-        progress(f"warm-start step {i}: {r.info['outer_iters']} outer steps")
+        progress(f"{label} step {i}: {r.info['outer_iters']} outer steps")
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / max(1, steps)
     info = infos[-1]
     assert info["status"] == 0 and info["eps_R"] <= args.tol, info
     rms = float(P_plain.double().pow(2).mean().sqrt())
     diff = float((P.double() - P_plain.double()).abs().max()) / rms
-    return {"s_per_solve": sec, "timed_solves": steps, "guess_s": t_guess / max(1, steps),
-            "outer_iters": info["outer_iters"],
-            "inner_iters": info["inner_iters_total"], "eps_R": info["eps_R"], "factor": factor,
-            "weights": os.path.relpath(args.weights, ROOT), "train": {k: net.meta[k] for k in net.meta},
-            "maxabs_vs_plain_rel_rms": diff}
+    out = {"s_per_solve": sec, "timed_solves": steps, "guess_s": t_guess / max(1, steps),
+           "outer_iters": info["outer_iters"], "inner_iters": info["inner_iters_total"], "eps_R": info["eps_R"],
+           "factor": ws.factor, "coarse_solve": ws.coarse, "maxabs_vs_plain_rel_rms": diff}
+    if ws.coarse:
+        out["coarse"] = dict(ws.last, tol=ws.coarse_tol, grid=[d // ws.factor for d in plan.dims],
+                             solver="fixed-point CG variant")
+    if ws.net is not None:
+        out["weights"] = os.path.relpath(args.weights, ROOT)
+        out["train"] = {k: ws.net.meta[k] for k in ws.net.meta}
+    return out
+
+
+def warm_start_legs(args, pi, plan, grads, P_plain, n, sec_plain):
+    """Three starts beside the zero start: the learned guess with the coarse
+    solve (the warm start), the learned guess alone, the coarse solve alone."""
+    from paper_2311_16935_amd.warmstart import UNet, WarmStart
+
+    net = UNet.from_file(args.weights)
+    factor = n // int(net.meta.get("train_n", 64))
+    legs = {}
+    for key, ws in (("learned_plus_coarse", WarmStart(net, factor, coarse=True)),
+                    ("learned_only", WarmStart(net, factor)),
+                    ("coarse_only", WarmStart(None, factor, coarse=True))):
+        legs[key] = warm_start_leg(args, pi, plan, grads, P_plain, n, ws, key)
+        legs[key]["reduction_vs_plain"] = 1.0 - legs[key]["s_per_solve"] / sec_plain
+        ws.close()
+    out = dict(legs["learned_plus_coarse"])
+    out["legs"] = legs
+    return out
 
 
 def variant_leg(args, pi, grads, P_plain, dims, mask, spacing, weights_ok, cc=False):
@@ -765,7 +785,7 @@ def main():
     warm = None
     weights_ok = not args.no_warm and os.path.exists(args.weights) and len(dims) == 3
     if weights_ok:
-        warm = warm_start_leg(args, pi, plan, grads, P_plain, n)
+        warm = warm_start_legs(args, pi, plan, grads, P_plain, n, sec)
     variant = None
     if not args.no_variant:
         variant = variant_leg(args, pi, grads, P_plain, dims, mask, w.spacing, weights_ok, cc)

@@ -119,6 +119,16 @@ pi_status pu_prepare_input(const float *gx, const float *gy, const float *gz, co
                            void *stream);
 
 /*
+ * Coarse-grid view of a gradient field for the coarse solve of the warm
+ * start: per block of factor^3 cells (factor^2 in 2-D, gz NULL), the FP32
+ * mean of each component over the block's data cells (0 where none), written
+ * to ox, oy, oz (oz ignored in 2-D) in the solver's layout of the coarse grid
+ * (nx/f, ny/f[, nz/f]).  dims must be divisible by factor.
+ */
+pi_status pu_block_mean(const float *gx, const float *gy, const float *gz, const uint8_t *mask,
+                        const int64_t dims[3], int32_t factor, float *ox, float *oy, float *oz, void *stream);
+
+/*
  * Network output -> solver grid: trilinear interpolation of the cell-centred
  * coarse field (FP32 [d/f][h/f][w/f]) onto the fine cells, times scale,
  * written as float or double (fp64 = 1) in the solver's layout.

@@ -470,6 +470,31 @@ __global__ void k_prepare(const float *gx, const float *gy, const float *gz, con
   out.p[elem(out, i, 3)] = f2bf(cnt / (float)(f * f * fz));
 }
 
+// coarse cell (z, y, x): FP32 means of each gradient component over the data
+// cells of its block (0 where the block holds none)
+__global__ void k_block_mean(const float *gx, const float *gy, const float *gz, const uint8_t *mask, int nx, int ny,
+                             int nz, int f, int fz, float *ox, float *oy, float *oz) {
+  const int cnx = nx / f, cny = ny / f, cnz = nz / fz;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)cnx * cny * cnz) return;
+  const int cx = (int)(i % cnx), cy = (int)((i / cnx) % cny), cz = (int)(i / ((int64_t)cnx * cny));
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, cnt = 0.f;
+  for (int dz = 0; dz < fz; ++dz)
+    for (int dy = 0; dy < f; ++dy)
+      for (int dx = 0; dx < f; ++dx) {
+        const int64_t c = ((int64_t)(cz * fz + dz) * ny + cy * f + dy) * nx + cx * f + dx;
+        if (mask && !mask[c]) continue;
+        s0 += gx[c];
+        s1 += gy[c];
+        if (gz) s2 += gz[c];
+        cnt += 1.f;
+      }
+  const float inv = cnt > 0.f ? 1.f / cnt : 0.f;
+  ox[i] = s0 * inv;
+  oy[i] = s1 * inv;
+  if (oz) oz[i] = s2 * inv;
+}
+
 __device__ inline float lerp_idx(int fine, int f, int n, int &i0) {
   // cell-centred: fine centre (fine + 1/2) / f - 1/2 in coarse index units
   float u = ((float)fine + 0.5f) / (float)f - 0.5f;
@@ -692,6 +717,19 @@ extern "C" pi_status pu_prepare_input(const float *gx, const float *gy, const fl
   const int64_t cells = (int64_t)out->d * out->h * out->w;
   k_prepare<<<blocks(cells), dim3(256), 0, (hipStream_t)stream>>>(gx, gy, gz, mask, (int)nx, (int)ny, (int)nz, factor,
                                                                   fz, scale, tens(out));
+  return PU_LAUNCHED;
+}
+
+extern "C" pi_status pu_block_mean(const float *gx, const float *gy, const float *gz, const uint8_t *mask,
+                                   const int64_t dims[3], int32_t factor, float *ox, float *oy, float *oz,
+                                   void *stream) {
+  if (!gx || !gy || !dims || factor < 1 || !ox || !oy || (gz && !oz)) return PI_ERR_INVALID_ARG;
+  const int64_t nx = dims[0], ny = dims[1], nz = dims[2] > 0 ? dims[2] : 1;
+  const int fz = gz ? factor : 1;
+  if (nx % factor || ny % factor || nz % fz) return PI_ERR_INVALID_ARG;
+  const int64_t cells = (nx / factor) * (ny / factor) * (nz / fz);
+  k_block_mean<<<blocks(cells), dim3(256), 0, (hipStream_t)stream>>>(gx, gy, gz, mask, (int)nx, (int)ny, (int)nz,
+                                                                     factor, fz, ox, oy, gz ? oz : nullptr);
   return PU_LAUNCHED;
 }
 

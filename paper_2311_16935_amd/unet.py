@@ -15,7 +15,7 @@ from . import PI_OK, PiError, _stream, lib
 
 EXPORTED = ("pu_conv", "pu_wgrad_work_floats", "pu_conv_wgrad", "pu_transpose_taps", "pu_relu_backward",
             "pu_pool", "pu_pool_backward", "pu_head", "pu_head_backward", "pu_mse", "pu_adam",
-            "pu_prepare_input", "pu_upsample_output", "pu_grad_rms")
+            "pu_prepare_input", "pu_block_mean", "pu_upsample_output", "pu_grad_rms")
 
 # FP32 scratch sizes the element-wise reductions need (see the header)
 HEAD_WORK_FLOATS = lambda c: 1025 * (c + 1)  # noqa: E731
@@ -46,6 +46,7 @@ def _sig():
         "pu_mse": [vp, vp, vp, i64, vp, vp, vp, vp],
         "pu_adam": [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, i32, vp],
         "pu_prepare_input": [vp, vp, vp, vp, L3, i32, f32, T, vp],
+        "pu_block_mean": [vp, vp, vp, vp, L3, i32, vp, vp, vp, vp],
         "pu_upsample_output": [vp, L3, i32, f32, vp, i32, vp],
         "pu_grad_rms": [vp, vp, vp, vp, i64, vp, vp, vp],
     }
@@ -143,6 +144,12 @@ def pu_prepare_input(gx, gy, gz, mask, dims, factor, scale, out: PuTensor, strea
     d = (ctypes.c_int64 * 3)(*(list(int(v) for v in dims) + [1] * (3 - len(dims))))
     _ok(lib.pu_prepare_input(_p(gx), _p(gy), _p(gz), _p(mask), d, int(factor), float(scale), ctypes.byref(out),
                              _stream(stream)), "pu_prepare_input")
+
+
+def pu_block_mean(gx, gy, gz, mask, dims, factor, ox, oy, oz, stream=None):
+    d = (ctypes.c_int64 * 3)(*(list(int(v) for v in dims) + [1] * (3 - len(dims))))
+    _ok(lib.pu_block_mean(_p(gx), _p(gy), _p(gz), _p(mask), d, int(factor), _p(ox), _p(oy), _p(oz),
+                          _stream(stream)), "pu_block_mean")
 
 
 def pu_upsample_output(coarse, dims, factor, scale, P, fp64=False, stream=None):

@@ -297,28 +297,81 @@ def _net_scale(spacing, factor):
 
 
 class WarmStart:
-    """Guess {P^0} for a plan with a trained network at grid/factor."""
+    """Guess {P^0} for a plan: a trained network at grid/factor and, with
+    ``coarse``, a solve of the same problem on that coarse grid.
 
-    def __init__(self, net: UNet, factor: int):
+    Network only: the network's output, trilinearly upsampled.
+
+    ``coarse``: the gradient field is block-averaged onto the network grid
+    (grid / factor), that coarse problem is solved with the fixed-point CG
+    variant (PI_FIXED_POINT_CG, to eps_R <= coarse_tol) starting from the
+    network's output (or from zero when ``net`` is None), and the coarse
+    answer is upsampled.  The paper's iteration is slow on the smooth part
+    of its error, which a coarse solve supplies cheaply; the network in turn
+    is a good start for that CG solve, which treats all scales alike.
+    FP32 plans without a mask only."""
+
+    def __init__(self, net: UNet | None, factor: int, coarse: bool = False, coarse_tol: float = 1e-6):
+        if net is None and not coarse:
+            raise ValueError("a warm start needs a network or the coarse solve")
         self.net, self.factor = net, int(factor)
-        self._rms = torch.zeros(1, dtype=torch.float32, device=net.device)
+        self.coarse, self.coarse_tol = bool(coarse), float(coarse_tol)
+        dev = net.device if net is not None else torch.device("cuda:0")
+        self._rms = torch.zeros(1, dtype=torch.float32, device=dev)
+        self._small = net.small if net is not None else torch.zeros(U.RMS_WORK_FLOATS, dtype=torch.float32, device=dev)
+        self._coarse = {}  # (dims, spacing) -> (plan, gradient buffers, P buffer)
+        self.last = {}     # what the last guess did (coarse outer/inner steps)
+
+    def _coarse_for(self, plan: Plan, device):
+        f = self.factor
+        cdims = tuple(d // f for d in plan.dims)
+        key = (cdims, plan.spacing)
+        if key not in self._coarse:
+            cp = Plan(cdims, tuple(h * f for h in plan.spacing), fixed_point=True)
+            cp.autotune(reps=3)
+            shape = cp.shape
+            gc = [torch.zeros(shape, dtype=torch.float32, device=device) for _ in range(plan.ndim)]
+            self._coarse[key] = (cp, gc, torch.zeros(shape, dtype=torch.float32, device=device))
+        return self._coarse[key]
 
     def guess(self, plan: Plan, grads, P, mask=None, stream=None):
-        if plan.ndim != 3:
-            raise ValueError("the warm-start network is 3-D")
-        nx, ny, nz = plan.dims
+        nx, ny, nz = (tuple(plan.dims) + (1,))[:3]
         f = self.factor
-        res = (nz // f, ny // f, nx // f)
-        B = self.net.buffers(1, res)
+        if self.net is not None and plan.ndim != 3:
+            raise ValueError("the warm-start network is 3-D")
+        if self.coarse and (plan.fp64 or mask is not None):
+            raise ValueError("the coarse solve of the warm start takes FP32 plans without a mask")
         count = nx * ny * nz
-        U.pu_grad_rms(grads[0], grads[1], grads[2], mask, count, self._rms, self.net.small, stream)
-        rms = float(self._rms.item())
-        if not rms > 0.0:
-            raise ValueError("gradient field is zero")
-        U.pu_prepare_input(grads[0], grads[1], grads[2], mask, plan.dims, f, 1.0 / rms, U.tensor(B["x0"]), stream)
-        y = self.net.forward(B, stream)
-        U.pu_upsample_output(y, plan.dims, f, rms * _net_scale(plan.spacing, f), P, plan.fp64, stream)
+        y = None
+        if self.net is not None:
+            res = (nz // f, ny // f, nx // f)
+            B = self.net.buffers(1, res)
+            U.pu_grad_rms(grads[0], grads[1], grads[2], mask, count, self._rms, self._small, stream)
+            rms = float(self._rms.item())
+            if not rms > 0.0:
+                raise ValueError("gradient field is zero")
+            U.pu_prepare_input(grads[0], grads[1], grads[2], mask, plan.dims, f, 1.0 / rms, U.tensor(B["x0"]),
+                               stream)
+            y = self.net.forward(B, stream)
+            yscale = rms * _net_scale(plan.spacing, f)
+        if not self.coarse:
+            U.pu_upsample_output(y, plan.dims, f, yscale, P, plan.fp64, stream)
+            return P
+        cp, gc, Pc = self._coarse_for(plan, grads[0].device)
+        U.pu_block_mean(grads[0], grads[1], grads[2] if plan.ndim == 3 else None, None, plan.dims, f, gc[0], gc[1],
+                        gc[2] if plan.ndim == 3 else None, stream)
+        if y is not None:  # the network's answer on the coarse grid starts the coarse solve
+            U.pu_upsample_output(y, cp.dims, 1, yscale, Pc, False, stream)
+        r = cp.solve(gc, P=Pc, tol=self.coarse_tol, max_iter=1000, warm_start=y is not None, stream=stream)
+        self.last = {"coarse_outer": r.info["outer_iters"], "coarse_inner": r.info["inner_iters_total"],
+                     "coarse_eps_R": r.info["eps_R"]}
+        U.pu_upsample_output(Pc, plan.dims, f, 1.0, P, plan.fp64, stream)
         return P
+
+    def close(self):
+        for cp, _, _ in self._coarse.values():
+            cp.close()
+        self._coarse.clear()
 
     def solve(self, plan: Plan, grads, P=None, tol=1e-6, max_iter=10**7, mask=None):
         if P is None:

@@ -253,6 +253,11 @@ def test_prepare_input_upsample_and_rms():
         P = torch.zeros((nz, ny, nx), dtype=torch.float64 if fp64 else torch.float32, device=DEV)
         U.pu_upsample_output(_dev_f(coarse), (nx, ny, nz), f, 3.0, P, fp64)
         _check(_host(P), 3.0 * O.upsample_linear(coarse, f), False, f"upsample fp64={fp64}")
+    # FP32 coarse-grid means of the gradient components (the coarse solve's input)
+    co = [torch.zeros((nz // f, ny // f, nx // f), dtype=torch.float32, device=DEV) for _ in range(3)]
+    U.pu_block_mean(gd[0], gd[1], gd[2], md, (nx, ny, nz), f, co[0], co[1], co[2])
+    for k in range(3):
+        assert np.abs(_host(co[k]) - ref[..., k] / 0.5).max() <= 1e-5 * (1 + np.abs(ref[..., k]).max() / 0.5), k
     # 2-D grid: one plane, no z component
     out2 = torch.zeros((1, 1, ny // f, nx // f, 4), dtype=torch.bfloat16, device=DEV)
     U.pu_prepare_input(gd[0][0], gd[1][0], None, md[0], (nx, ny), f, 1.0, U.tensor(out2))
