@@ -131,10 +131,14 @@ pi_status pu_block_mean(const float *gx, const float *gy, const float *gz, const
 /*
  * Network output -> solver grid: trilinear interpolation of the cell-centred
  * coarse field (FP32 [d/f][h/f][w/f]) onto the fine cells, times scale,
- * written as float or double (fp64 = 1) in the solver's layout.
+ * written as float, or as double with PU_OUT_FP64, in the solver's layout;
+ * with PU_OUT_ADD added to what P holds instead of replacing it.  factor 1
+ * copies (scaled).
  */
+#define PU_OUT_FP64 0x1
+#define PU_OUT_ADD 0x2
 pi_status pu_upsample_output(const float *coarse, const int64_t dims[3], int32_t factor, float scale, void *P,
-                             int32_t fp64, void *stream);
+                             int32_t flags, void *stream);
 
 /*
  * Normalisation of the network input: rms = sqrt(sum |g|^2 / valid cells) over

@@ -129,12 +129,25 @@ def block_mean(fields, mask, factor):
 
 def upsample_linear(coarse, factor):
     """Cell-centred multilinear interpolation of a coarse field onto a grid
-    `factor` times finer along every axis, constant beyond the outermost
-    coarse centres; one 1-D linear interpolation (numpy.interp) per axis."""
+    `factor` times finer along every axis, one 1-D interpolation per axis:
+    a fine centre at coarse coordinate u = (i + 1/2) / factor - 1/2 takes the
+    straight line through the two coarse centres around it, and the line
+    through the two outermost ones beyond them (so a field linear in the
+    coordinates is reproduced up to the grid's edge); an axis of one coarse
+    cell is constant."""
     out = np.asarray(coarse, float)
     for ax in range(out.ndim):
         n = out.shape[ax]
-        xc = np.arange(n, dtype=float)
-        xf = (np.arange(n * factor) + 0.5) / factor - 0.5
-        out = np.apply_along_axis(lambda v: np.interp(xf, xc, v), ax, out)
+        u = (np.arange(n * factor) + 0.5) / factor - 0.5
+        if n == 1:
+            out = np.repeat(out, factor, axis=ax)
+            continue
+        i0 = np.clip(np.floor(u).astype(int), 0, n - 2)
+        t = u - i0
+        a = np.take(out, i0, axis=ax)
+        b = np.take(out, i0 + 1, axis=ax)
+        shape = [1] * out.ndim
+        shape[ax] = -1
+        t = t.reshape(shape)
+        out = a + t * (b - a)
     return out

@@ -496,15 +496,18 @@ __global__ void k_block_mean(const float *gx, const float *gy, const float *gz, 
 }
 
 __device__ inline float lerp_idx(int fine, int f, int n, int &i0) {
-  // cell-centred: fine centre (fine + 1/2) / f - 1/2 in coarse index units
-  float u = ((float)fine + 0.5f) / (float)f - 0.5f;
-  u = fminf(fmaxf(u, 0.f), (float)(n - 1));
-  i0 = min((int)floorf(u), max(n - 2, 0));
+  // cell-centred: fine centre (fine + 1/2) / f - 1/2 in coarse index units;
+  // beyond the outermost coarse centres the line through the two outermost
+  // ones continues (weight outside [0, 1]), so linear fields are exact up to
+  // the grid's edge -- where the solver reads the start (the first cells of
+  // the rays, [W^n])
+  const float u = ((float)fine + 0.5f) / (float)f - 0.5f;
+  i0 = min(max((int)floorf(u), 0), max(n - 2, 0));
   return n > 1 ? u - (float)i0 : 0.f;
 }
 
 __global__ void k_upsample(const float *coarse, int nx, int ny, int nz, int f, int fz, float scale, void *P,
-                           int fp64) {
+                           int fp64, int accumulate) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t cells = (int64_t)nx * ny * nz;
   if (i >= cells) return;
@@ -521,9 +524,9 @@ __global__ void k_upsample(const float *coarse, int nx, int ny, int nz, int f, i
   const float c11 = at(z1, y1, x0) * (1 - tx) + at(z1, y1, x1) * tx;
   const float v = scale * ((c00 * (1 - ty) + c01 * ty) * (1 - tz) + (c10 * (1 - ty) + c11 * ty) * tz);
   if (fp64)
-    ((double *)P)[i] = (double)v;
+    ((double *)P)[i] = (accumulate ? ((double *)P)[i] : 0.0) + (double)v;
   else
-    ((float *)P)[i] = v;
+    ((float *)P)[i] = (accumulate ? ((float *)P)[i] : 0.f) + v;
 }
 
 inline unsigned blocks(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
@@ -734,13 +737,14 @@ extern "C" pi_status pu_block_mean(const float *gx, const float *gy, const float
 }
 
 extern "C" pi_status pu_upsample_output(const float *coarse, const int64_t dims[3], int32_t factor, float scale,
-                                        void *P, int32_t fp64, void *stream) {
-  if (!coarse || !dims || !P || factor < 1) return PI_ERR_INVALID_ARG;
+                                        void *P, int32_t flags, void *stream) {
+  if (!coarse || !dims || !P || factor < 1 || (flags & ~(PU_OUT_FP64 | PU_OUT_ADD))) return PI_ERR_INVALID_ARG;
   const int64_t nx = dims[0], ny = dims[1], nz = dims[2] > 0 ? dims[2] : 1;
   const int fz = nz > 1 ? factor : 1;
   if (nx % factor || ny % factor || nz % fz) return PI_ERR_INVALID_ARG;
   k_upsample<<<blocks(nx * ny * nz), dim3(256), 0, (hipStream_t)stream>>>(coarse, (int)nx, (int)ny, (int)nz, factor,
-                                                                          fz, scale, P, fp64);
+                                                                          fz, scale, P, (flags & PU_OUT_FP64) != 0,
+                                                                          (flags & PU_OUT_ADD) != 0);
   return PU_LAUNCHED;
 }
 

@@ -152,9 +152,13 @@ def pu_block_mean(gx, gy, gz, mask, dims, factor, ox, oy, oz, stream=None):
                           _stream(stream)), "pu_block_mean")
 
 
-def pu_upsample_output(coarse, dims, factor, scale, P, fp64=False, stream=None):
+PU_OUT_FP64, PU_OUT_ADD = 0x1, 0x2
+
+
+def pu_upsample_output(coarse, dims, factor, scale, P, fp64=False, stream=None, add=False):
     d = (ctypes.c_int64 * 3)(*(list(int(v) for v in dims) + [1] * (3 - len(dims))))
-    _ok(lib.pu_upsample_output(_p(coarse), d, int(factor), float(scale), _p(P), int(fp64), _stream(stream)),
+    flags = (PU_OUT_FP64 if fp64 else 0) | (PU_OUT_ADD if add else 0)
+    _ok(lib.pu_upsample_output(_p(coarse), d, int(factor), float(scale), _p(P), flags, _stream(stream)),
         "pu_upsample_output")
 
 

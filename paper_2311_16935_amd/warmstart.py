@@ -306,9 +306,13 @@ class WarmStart:
     (grid / factor), that coarse problem is solved with the fixed-point CG
     variant (PI_FIXED_POINT_CG, to eps_R <= coarse_tol) starting from the
     network's output (or from zero when ``net`` is None), and the coarse
-    answer is upsampled.  The paper's iteration is slow on the smooth part
-    of its error, which a coarse solve supplies cheaply; the network in turn
-    is a good start for that CG solve, which treats all scales alike.
+    answer is upsampled.  In Eq. MatrixEquation the previous iterate enters
+    only through [W^n], whose weights count rays that start at the
+    neighbour, i.e. at cells on the edge of the data: after the first outer
+    step the iteration depends on the start only through its values there.
+    The coarse solve gives those values to second order once the upsampling
+    continues linearly to the grid's edge (pu_upsample_output); the network
+    is a good start for the coarse CG, which treats all scales alike.
     FP32 plans without a mask only."""
 
     def __init__(self, net: UNet | None, factor: int, coarse: bool = False, coarse_tol: float = 1e-6):

@@ -253,6 +253,8 @@ def test_prepare_input_upsample_and_rms():
         P = torch.zeros((nz, ny, nx), dtype=torch.float64 if fp64 else torch.float32, device=DEV)
         U.pu_upsample_output(_dev_f(coarse), (nx, ny, nz), f, 3.0, P, fp64)
         _check(_host(P), 3.0 * O.upsample_linear(coarse, f), False, f"upsample fp64={fp64}")
+        U.pu_upsample_output(_dev_f(coarse), (nx, ny, nz), f, -1.0, P, fp64, add=True)
+        _check(_host(P), 2.0 * O.upsample_linear(coarse, f), False, f"upsample add fp64={fp64}")
     # FP32 coarse-grid means of the gradient components (the coarse solve's input)
     co = [torch.zeros((nz // f, ny // f, nx // f), dtype=torch.float32, device=DEV) for _ in range(3)]
     U.pu_block_mean(gd[0], gd[1], gd[2], md, (nx, ny, nz), f, co[0], co[1], co[2])

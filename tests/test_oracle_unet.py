@@ -121,16 +121,35 @@ def test_block_mean_against_loops_and_invariants():
     assert np.all(full[..., 1] == 1.0)
 
 
-def test_upsample_is_exact_on_linear_fields_inside_and_constant_outside():
+def test_upsample_is_exact_on_linear_fields_up_to_the_edge():
     cz, cy, cx = np.meshgrid(np.arange(3.0), np.arange(4.0), np.arange(5.0), indexing="ij")
     coarse = 0.5 + 2.0 * cx - 1.5 * cy + 0.25 * cz
     f = 4
     up = U.upsample_linear(coarse, f)
     assert up.shape == (12, 16, 20)
-    for (k, j, i) in [(5, 7, 9), (4, 2, 17), (6, 13, 3)]:
-        u = [(v + 0.5) / f - 0.5 for v in (k, j, i)]
-        assert up[k, j, i] == pytest.approx(0.5 + 2.0 * u[2] - 1.5 * u[1] + 0.25 * u[0], abs=1e-12)
-    # beyond the outermost centres the field is held constant
-    assert up[0, 0, 0] == pytest.approx(coarse[0, 0, 0])
-    assert up[-1, -1, -1] == pytest.approx(coarse[-1, -1, -1])
+    # every fine centre, the half coarse cell beyond the outermost coarse
+    # centres included: the linear field at its coarse coordinate
+    k, j, i = np.meshgrid(np.arange(12.0), np.arange(16.0), np.arange(20.0), indexing="ij")
+    u = [(v + 0.5) / f - 0.5 for v in (k, j, i)]
+    assert np.abs(up - (0.5 + 2.0 * u[2] - 1.5 * u[1] + 0.25 * u[0])).max() < 1e-12
+    assert up[0, 0, 0] == pytest.approx(0.5 - 2.0 * 0.375 + 1.5 * 0.375 - 0.25 * 0.375)
     assert np.allclose(U.upsample_linear(np.full((2, 3), 7.0), 3), 7.0)
+    # an axis of one coarse cell is constant along it
+    assert np.allclose(U.upsample_linear(np.arange(3.0)[None, :], 2)[:, 0], -0.25)
+
+
+def test_upsample_against_a_direct_double_loop():
+    """Interpolation weights written out per fine cell (2-D), independently
+    of the per-axis form."""
+    rng = np.random.default_rng(5)
+    c = rng.normal(size=(3, 4))
+    f = 2
+    up = U.upsample_linear(c, f)
+    for y in range(6):
+        for x in range(8):
+            uy, ux = (y + 0.5) / f - 0.5, (x + 0.5) / f - 0.5
+            y0, x0 = min(max(int(np.floor(uy)), 0), 1), min(max(int(np.floor(ux)), 0), 2)
+            ty, tx = uy - y0, ux - x0
+            ref = ((1 - ty) * (1 - tx) * c[y0, x0] + (1 - ty) * tx * c[y0, x0 + 1] + ty * (1 - tx) * c[y0 + 1, x0] +
+                   ty * tx * c[y0 + 1, x0 + 1])
+            assert up[y, x] == pytest.approx(ref, abs=1e-12)
