@@ -208,7 +208,7 @@ pi_status pi_solve_batched(int64_t count, const pi_plan_t *plans, const void *co
  * harness that forbids hipMalloc): the same arguments, kernels and results,
  * but the per-call device buffers (instance records, per-instance scalars,
  * partial sums, block tables) live in one static device array of the
- * library (about 15 MB on every GPU it runs on, held until the process
+ * library (about 32 MB on every GPU it runs on, held until the process
  * ends: room for the limits below).  The call allocates no device or pinned host memory and
  * creates no stream, event or graph: the outer steps are launched directly
  * on `stream` and the convergence flags are copied back to pageable host

@@ -31,6 +31,12 @@ constexpr int kSegCells = 65536; // gauge segment length (cells)
 constexpr int kShapes = 10;      // stencil launch shapes: (2-D, 3-D) x (1, 4 cells per lane) x (codes read,
                                  // derived), and the 2-D cell-centred scheme with 1 or 4 cells per lane
 constexpr int kShapeCC = 8;
+// An instance of at most this many blocks runs its inner CG passes without a
+// finalize kernel: every block of a pass re-sums the previous pass's partial
+// sums (a few KB from L2) to get alpha and beta.  Larger instances keep the
+// finalize, which bounds those redundant reads.
+constexpr int kInlineMaxBlocks = 2048;
+constexpr int32_t kNoStop = 1 << 30;
 constexpr int kShapeCC4 = 9;
 
 // Launch shape of an instance: bit 0 = 3-D, bit 1 = four cells per lane,
@@ -115,6 +121,11 @@ struct Inst {
   int64_t sm;       // stride of the marching axis
   int64_t srow;     // stride between stacked strips (nx in 3-D, 0 in 2-D)
   int32_t part_base;// first slot of this instance in the partial-sum array
+  int32_t part_stride; // slots of one partial-sum array; the CG passes use the
+                       // two arrays after the first one, by pass parity
+  int32_t bicg;     // inner solver is BiCGStab (else the single-pass CG)
+  int32_t cg_inline;// the CG passes take alpha and beta from the previous
+                    // pass's partials themselves (no finalize kernel)
   int32_t ncomp;    // connected groups of data cells
   int32_t inner_iters; // inner Krylov iterations per outer step
   int32_t inner_op; // operator of the inner solve: 0 [W^{n+1}], 1 [W^{n+1}] - [W^n]
@@ -173,22 +184,19 @@ struct State {
   double red[4];    // scratch for the last block's results
   int64_t outer;
   int64_t inner_total;
-  int32_t inner;    // inner iteration inside the current outer step
-  int32_t first;    // next search direction is the residual itself
-  int32_t pcur;     // current p buffer
+  int32_t inner;    // BiCGStab: inner iteration inside the current outer step
+  int32_t first;    // BiCGStab: next search direction is the residual itself
+  int32_t pcur;     // BiCGStab: current p buffer
   int32_t Pcur;     // current P buffer
   int32_t have_delta;
   int32_t done;
   int32_t status;   // pi_status
   int32_t nonfinite;
-  int32_t tail;     // CG: the last inner iteration's alpha p is still to be
-                    // added to the correction (the next inner pass or the outer
-                    // kernel does it)
-  int32_t rcur;     // CG: current residual buffer (res / res1)
-  int32_t qcur;     // CG: current M p buffer (q / q1)
-  int32_t dvalid;   // the correction buffer holds this outer step's sum: an
-                    // inner pass has written it since the outer step began
-                    // (the outer kernel reads it only then)
+  int32_t stop_at;  // CG: first pass of the current outer step that did not
+                    // run because the inner solve had converged (kNoStop if
+                    // none); passes 0 .. min(stop_at, inner_iters) - 1 ran
+  int32_t dvalid;   // BiCGStab: the correction buffer holds this outer step's
+                    // sum (an update has run since the outer step began)
 };
 
 }  // namespace pi

@@ -30,7 +30,7 @@ struct LaunchArgs {
   double *part;
   int nblocks;          // entries of tab (grid size)
   hipStream_t stream;
-  int iarg;             // K_INIT: warm start flag; K_APPLY: operator
+  int iarg;             // K_INIT: warm start flag; K_APPLY: operator; K_CG_STEP: pass index
   const void *x;        // K_APPLY input
   void *y;              // K_APPLY output
 };
@@ -40,7 +40,8 @@ hipError_t launch(KernelId k, bool fp64, int shape, const LaunchArgs &la);
 // Kernels that leave per-block partial sums, and the per-instance finalize
 // (grid = count instances) that turns them into the instances' scalars.
 bool reduces(KernelId k);
-hipError_t launch_finalize(KernelId k, const Inst *insts, State *sts, const double *part, int count, hipStream_t s);
+hipError_t launch_finalize(KernelId k, const Inst *insts, State *sts, const double *part, int count, hipStream_t s,
+                           int iarg = 0);
 
 // Plan-time kernel: packed per-cell counter codes from the device mask.
 hipError_t launch_codes(int ndim, int nx, int ny, int nz, const uint8_t *mask, uint32_t *code, hipStream_t s);

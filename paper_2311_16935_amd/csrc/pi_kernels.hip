@@ -489,6 +489,57 @@ __device__ inline void publish(const Inst &in, double *part, int lb, double (&v)
   }
 }
 
+// The four sums (p.q, r.q, q.q, r.r) that the blocks of inner CG pass j of
+// this instance wrote, added in a fixed order; every thread gets the totals.
+// Pass j's partials sit in partial array 1 + (j & 1).
+__device__ inline void cg_partials(const Inst &in, const double *part, int j, double (&s)[4]) {
+  __shared__ double lds[kWavesPerBlock * 4];
+  __shared__ double tot[4];
+  const double2 *slots =
+      reinterpret_cast<const double2 *>(part + ((int64_t)(1 + (j & 1)) * in.part_stride + in.part_base) * 4);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s[k] = 0.0;
+  for (int i = threadIdx.x; i < in.nblocks; i += kBlock) {
+    const double2 a = slots[2 * i], b = slots[2 * i + 1];
+    s[0] += a.x;
+    s[1] += a.y;
+    s[2] += b.x;
+    s[3] += b.y;
+  }
+  block_sum<4>(s, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tot[k] = s[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s[k] = tot[k];
+}
+
+// From the sums of CG iteration j: alpha_j = r.r / p.q and, with
+// |r_j - alpha_j q_j|^2 = r.r - 2 alpha_j r.q + alpha_j^2 q.q, beta_{j+1}.
+// The fixed-point variant's inner solve stops once that residual is well
+// below the tolerance (the FP64 outer step then confirms it), or once it is
+// as small as the vector precision can resolve: beyond that only the
+// residual's rounding-level constant part is left, which the singular
+// operator cannot reduce (p.q -> 0 and alpha would blow up); the next outer
+// step restarts from the FP64 residual.
+struct CgScalars {
+  double al, be;
+  bool stop;
+};
+__device__ inline CgScalars cg_scalars(const Inst &in, const State *st, const double (&s)[4]) {
+  const double pq = s[0], rq = s[1], qq = s[2], rr = s[3];
+  const double al = pq != 0.0 ? rr / pq : 0.0;
+  double rn = rr - 2.0 * al * rq + al * al * qq;
+  if (!(rn > 0.0)) rn = 0.0;
+  CgScalars c;
+  c.al = al;
+  c.be = rr != 0.0 ? rn / rr : 0.0;
+  c.stop = in.inner_op != 0 && (rn <= 0.25 * in.tol * in.tol * st->normS2 || rn <= in.inner_floor * st->rr0);
+  return c;
+}
+
 template <typename T>
 __device__ inline void load_lut(const double (*src)[kStates], T (*dst)[kStates]) {
   for (int i = threadIdx.x; i < 6 * kStates; i += kBlock) dst[i / kStates][i % kStates] = (T)src[i / kStates][i % kStates];
@@ -600,6 +651,47 @@ __global__ __launch_bounds__(kBlock) void k_source(const BlockEnt *tab, const In
 // ---------------------------------------------------------------------------
 // outer step: P^{n+1} = P^n + delta, r = S - (M - N) P^{n+1}, eps_R
 // ---------------------------------------------------------------------------
+// The inner solve's correction as the outer kernel folds it in:
+// delta = d + at * pt.  With CG, K = min(stop_at, inner_iters) passes ran;
+// pass K - 1 left its search direction in p[K & 1] and its alpha in its
+// partial sums (or, with a finalize kernel, in the state); the correction
+// sum d was written by passes 1 .. K - 1, so it is read only when K >= 2
+// (with K = 1 the buffer still holds the previous outer step's sum).
+// BiCGStab adds every update into d itself.  Uniform over the launch.
+template <typename T>
+struct Pending {
+  T at;
+  const PI_G T *pt;
+  bool use_d;
+};
+template <typename T>
+__device__ inline Pending<T> pending(const Inst &in, const State *st, const double *part) {
+  Pending<T> pd;
+  pd.at = T(0);
+  pd.pt = gp<T>(in.p[0]);
+  pd.use_d = false;
+  if (!st->have_delta) return pd;  // no inner solve yet
+  if (in.bicg) {
+    pd.use_d = st->dvalid != 0;
+    return pd;
+  }
+  const int K = min(st->stop_at, in.inner_iters);
+  pd.use_d = K >= 2;
+  if (K >= 1) {
+    double al;
+    if (in.cg_inline) {
+      double s[4];
+      cg_partials(in, part, K - 1, s);
+      al = s[0] != 0.0 ? s[3] / s[0] : 0.0;
+    } else {
+      al = st->alpha;
+    }
+    pd.at = (T)al;
+    pd.pt = gp<T>(in.p[K & 1]);
+  }
+  return pd;
+}
+
 // (M - N) is applied as sum_j a_j (P_C - P_J) over face neighbours holding
 // data: its off-diagonal entries are -(w_j^{n+1} + w_j^n) = -a_j and, since
 // all counters of a data cell add up to A_tot, its diagonal 1 - w_C^n equals
@@ -614,17 +706,13 @@ __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Ins
   const int cur = st->Pcur;
   const PI_G double *Pold = gp<double>(in.P[cur]);
   PI_G double *Pnew = gp<double>(in.P[cur ^ 1]);
-  // p is zero before the first inner solve and finite after it, so the
-  // fold needs no branch: at = 0 when nothing is pending
-  const T at = st->tail ? (T)st->alpha : T(0);
-  const PI_G T *pt = gp<T>(in.p[st->pcur]);
+  const Pending<T> pd = pending<T>(in, st, part);
+  const T at = pd.at;
+  const PI_G T *pt = pd.pt;
   const PI_G T *dl = gp<T>(in.d);
-  // the correction buffer is read only once an inner pass of this outer step
-  // has written it: an inner solve that stops after its first pass leaves
-  // the previous outer step's sum there (uniform over the launch)
-  const bool use_d = st->dvalid != 0;
+  const bool use_d = pd.use_d;
   const PI_G double *S = gp<double>(in.S64);
-  PI_G T *res = gp<T>(st->rcur ? in.res1 : in.res);
+  PI_G T *res = gp<T>(in.res);
   const int bits = dir_bits(ND);
   double a[6];
 #pragma unroll
@@ -768,48 +856,83 @@ __device__ inline T apply_l(const T *a, uint32_t cd, int bits, T vC, T vW, T vE,
 //   p_k = r_k + beta_k p_{k-1},            q_k = A p_k,
 // with A = [W^{n+1}] (or the fixed point's operator for the variant).  The
 // stencil needs p_k at the neighbours, so r, q and p are read there and
-// written to the other buffer of each pair.  Reductions: p.q, r.q, q.q, r.r;
-// the finalize takes alpha_k = r.r / p.q and beta_{k+1} from
-// |r_k - alpha_k q_k|^2 = r.r - 2 alpha_k r.q + alpha_k^2 q.q.  The first
-// iteration of an outer step has no update to fold (alpha ignored, beta 0),
-// and the second starts the correction from zero.
+// written to the other buffer of each pair (pass k reads buffer k & 1; the
+// outer kernel writes the residual into res, buffer 0).  Reductions: p.q,
+// r.q, q.q, r.r into partial array 1 + (k & 1).  alpha_{k-1} and beta_k come
+// from pass k-1's sums (cg_scalars): every block adds them up itself, or,
+// for instances of many blocks, a finalize kernel did so into the state.
+// Pass 0 has no update to fold (alpha, beta = 0) and pass 1 starts the
+// correction from zero.  k is the pass's index in the outer step, the same
+// for every instance of a launch.
 template <typename T>
 struct CgPass {
   const PI_G T *rold, *qold, *pold;
   PI_G T *rnew, *qnew, *pnew, *d;
   T al, be;
   bool rd_d, wr_d;
+  bool skip;
 };
 
 template <typename T>
-__device__ inline CgPass<T> cg_pass(const Inst &in, const State *st) {
+__device__ inline CgPass<T> cg_pass(const Inst &in, State *st, const double *part, int lb, int k) {
   CgPass<T> c;
-  c.rold = gp<T>(st->rcur ? in.res1 : in.res);
-  c.rnew = gp<T>(st->rcur ? in.res : in.res1);
-  c.qold = gp<T>(st->qcur ? in.q1 : in.q);
-  c.qnew = gp<T>(st->qcur ? in.q : in.q1);
-  c.pold = gp<T>(in.p[st->pcur]);
-  c.pnew = gp<T>(in.p[st->pcur ^ 1]);
+  // passes after the inner solve stopped have nothing to do.  With a
+  // finalize kernel, the stop at this pass was recorded before it started;
+  // without one, this pass's first block records it while the others run,
+  // so only earlier passes' stops are read here (the same value in every
+  // thread of the launch), and this pass decides its own below
+  c.skip = st->done != 0 || k >= in.inner_iters || st->stop_at < k || (!in.cg_inline && st->stop_at == k);
+  if (c.skip) return c;
+  double al = 0.0, be = 0.0;
+  if (k > 0) {
+    if (in.cg_inline) {
+      double s[4];
+      cg_partials(in, part, k - 1, s);
+      const CgScalars cs = cg_scalars(in, st, s);
+      if (cs.stop) {
+        if (lb == 0 && threadIdx.x == 0) st->stop_at = k;
+        c.skip = true;
+        return c;
+      }
+      al = cs.al;
+      be = cs.be;
+    } else {
+      al = st->alpha;
+      be = st->beta;
+    }
+  }
+  const int o = k & 1;
+  c.rold = gp<T>(o ? in.res1 : in.res);
+  c.rnew = gp<T>(o ? in.res : in.res1);
+  c.qold = gp<T>(o ? in.q1 : in.q);
+  c.qnew = gp<T>(o ? in.q : in.q1);
+  c.pold = gp<T>(in.p[o]);
+  c.pnew = gp<T>(in.p[o ^ 1]);
   c.d = gp<T>(in.d);
-  c.al = st->inner > 0 ? (T)st->alpha : T(0);
-  c.be = (T)st->beta;
-  c.wr_d = st->inner > 0;
-  c.rd_d = st->inner > 1;
+  c.al = (T)al;
+  c.be = (T)be;
+  c.wr_d = k > 0;
+  c.rd_d = k > 1;
   return c;
+}
+
+// partial array of CG pass k
+__device__ inline double *cg_part(const Inst &in, double *part, int k) {
+  return part + (int64_t)(1 + (k & 1)) * in.part_stride * 4;
 }
 
 template <typename T, int ND, int W, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_cg_step(const BlockEnt *tab, const Inst *insts, State *sts,
-                                                    double *part) {
+                                                    double *part, int kpass) {
   PI_PROLOGUE
-  if (skip_inner(in, st)) return;
+  const CgPass<T> cg = cg_pass<T>(in, st, part, e.lb, kpass);
+  if (cg.skip) return;
   __shared__ T lut[6][kStates];
   load_lut<T>(in.lut_np1, lut);
   T wi[6];  // interior weights, as the LUT holds them
 #pragma unroll
   for (int d = 0; d < 6; ++d) wi[d] = (T)in.lut_np1[d][interior_state<ND>()];
   const Walk wk = make_walk<W>(in, e.lb);
-  const CgPass<T> cg = cg_pass<T>(in, st);
   const int bits = dir_bits(ND);
   const bool opL = in.inner_op != 0;  // uniform over the launch
   T a[6];
@@ -866,7 +989,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_step(const BlockEnt *tab, const I
     if (cg.wr_d) stv<W>(cg.d, c, dv);
   };
   march<ND, W, GEN, T, Aux, Out>(wk, load, load1, aux, body, store);
-  publish<4>(in, part, e.lb, acc);
+  publish<4>(in, cg_part(in, part, kpass), e.lb, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1131,7 +1254,8 @@ __global__ __launch_bounds__(kBlock) void k_gauge_apply(const BlockEnt *tab, con
 // finalize: one block per instance sums the partials of the kernel that just
 // ran (fixed order) and updates the instance's scalars
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *sts, const double *part, int kind) {
+__global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *sts, const double *part, int kind,
+                                                    int kpass) {
   const Inst &in = insts[blockIdx.x];
   State *st = sts + blockIdx.x;
   switch (kind) {
@@ -1142,6 +1266,12 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
       break;
     case K_GAUGE_SUM:
       if (in.ncomp > 1) return;
+      break;
+    case K_CG_STEP:
+      // instances whose passes sum the partials themselves, and passes that
+      // did not run
+      if (in.cg_inline || st->done != 0 || kpass >= in.inner_iters || st->stop_at <= kpass) return;
+      part += (int64_t)(1 + (kpass & 1)) * in.part_stride * 4;
       break;
     default:
       if (skip_inner(in, st)) return;
@@ -1170,6 +1300,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
       break;
     case K_OUTER: {
       const bool hd = st->have_delta != 0;
+      // CG passes of the inner solve that just ended (BiCGStab counts its own)
+      if (hd && !in.bicg) st->inner_total += min(st->stop_at, in.inner_iters);
       const double epsR = st->normS2 > 0.0 ? sqrt(s[0] / st->normS2) : 0.0;
       st->epsR = epsR;
       if (hd) st->epsP = s[3] > 0.0 ? sqrt(s[2] / s[3]) : 0.0;
@@ -1188,7 +1320,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
         st->rr = s[1];
         st->rr0 = s[1];
         st->inner = 0;
-        st->tail = 0;
+        st->stop_at = kNoStop;
         st->dvalid = 0;
         st->first = 1;
         st->beta = 0.0;  // the first search direction is the residual itself
@@ -1201,31 +1333,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
       break;
     }
     case K_CG_STEP: {
-      const double pq = s[0], rq = s[1], qq = s[2], rr = s[3];
-      const double al = pq != 0.0 ? rr / pq : 0.0;
-      double rn = rr - 2.0 * al * rq + al * al * qq;  // |r_k - alpha_k q_k|^2
-      if (!(rn > 0.0)) rn = 0.0;
-      st->alpha = al;
-      st->beta = rr != 0.0 ? rn / rr : 0.0;
-      st->rr = rn;
-      st->pcur ^= 1;
-      st->qcur ^= 1;
-      st->rcur ^= 1;
-      st->first = 0;
-      st->tail = 1;  // alpha_k p_k is pending: the next pass or the outer kernel adds it
-      st->inner += 1;
-      st->inner_total += 1;
-      // every pass after the first writes the correction sum
-      if (st->inner >= 2) st->dvalid = 1;
-      // fixed-point variant: the inner residual is the outer residual of
-      // P + d, so the inner solve stops once it is well below the tolerance
-      // (the FP64 outer step then confirms it), or once it is as small as
-      // the vector precision can resolve: beyond that only the residual's
-      // rounding-level constant part is left, which the singular operator
-      // cannot reduce (p.q -> 0 and alpha would blow up); the next outer
-      // step restarts from the FP64 residual
-      if (in.inner_op != 0 && (rn <= 0.25 * in.tol * in.tol * st->normS2 || rn <= in.inner_floor * st->rr0))
-        st->inner = in.inner_iters;
+      const CgScalars cs = cg_scalars(in, st, s);
+      st->alpha = cs.al;
+      st->beta = cs.be;
+      if (cs.stop) st->stop_at = kpass + 1;
       break;
     }
     case K_BICG_P:
@@ -1507,15 +1618,13 @@ __global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const 
   const int cur = st->Pcur;
   const PI_G double *Pold = gp<double>(in.P[cur]);
   PI_G double *Pnew = gp<double>(in.P[cur ^ 1]);
-  const T at = st->tail ? (T)st->alpha : T(0);
-  const PI_G T *pt = gp<T>(in.p[st->pcur]);
+  const Pending<T> pd = pending<T>(in, st, part);
+  const T at = pd.at;
+  const PI_G T *pt = pd.pt;
   const PI_G T *dl = gp<T>(in.d);
-  // the correction buffer is read only once an inner pass of this outer step
-  // has written it: an inner solve that stops after its first pass leaves
-  // the previous outer step's sum there (uniform over the launch)
-  const bool use_d = st->dvalid != 0;
+  const bool use_d = pd.use_d;
   const PI_G double *S = gp<double>(in.S64);
-  PI_G T *res = gp<T>(st->rcur ? in.res1 : in.res);
+  PI_G T *res = gp<T>(in.res);
   double a[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) a[j] = in.cc_a[j];
@@ -1583,11 +1692,11 @@ __global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const 
 // k_cg_step, for the cell-centred scheme.
 template <typename T, int W>
 __global__ __launch_bounds__(kBlock) void k_cg_step_cc(const BlockEnt *tab, const Inst *insts, State *sts,
-                                                      double *part) {
+                                                      double *part, int kpass) {
   PI_PROLOGUE
-  if (skip_inner(in, st)) return;
+  const CgPass<T> cg = cg_pass<T>(in, st, part, e.lb, kpass);
+  if (cg.skip) return;
   const Walk wk = make_walk<W>(in, e.lb);
-  const CgPass<T> cg = cg_pass<T>(in, st);
   const bool opL = in.inner_op != 0;
   T a[8];
 #pragma unroll
@@ -1657,7 +1766,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_step_cc(const BlockEnt *tab, cons
     if (cg.wr_d) stv<W>(cg.d, c, dv);
   };
   march_cc<W, T, Aux, Out>(wk, load, load1, aux, body, store);
-  publish<4>(in, part, e.lb, acc);
+  publish<4>(in, cg_part(in, part, kpass), e.lb, acc);
 }
 
 // y = M x, N x or (M - N) x for pi_apply
@@ -1748,7 +1857,7 @@ static hipError_t launch_t(KernelId k, int shape, const LaunchArgs &la) {
       else k_source<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
       break;
     case K_OUTER: PI_MARCH(k_outer, PI_ARGS); break;
-    case K_CG_STEP: PI_MARCH(k_cg_step, PI_ARGS); break;
+    case K_CG_STEP: PI_MARCH(k_cg_step, PI_ARGS, la.iarg); break;
     case K_BICG_P:
       if (shape == kShapeCC || shape == kShapeCC4) return hipErrorInvalidValue;  // CG only
       PI_MARCH8(k_bicg_spmv_p, PI_ARGS);
@@ -1786,10 +1895,10 @@ bool reduces(KernelId k) {
   }
 }
 
-hipError_t launch_finalize(KernelId k, const Inst *insts, State *sts, const double *part, int count,
-                           hipStream_t s) {
+hipError_t launch_finalize(KernelId k, const Inst *insts, State *sts, const double *part, int count, hipStream_t s,
+                           int iarg) {
   if (count <= 0) return hipSuccess;
-  k_finalize<<<dim3(count), dim3(kBlock), 0, s>>>(insts, sts, part, (int)k);
+  k_finalize<<<dim3(count), dim3(kBlock), 0, s>>>(insts, sts, part, (int)k, iarg);
   return hipGetLastError();
 }
 

@@ -435,8 +435,12 @@ hipError_t plan_tables(pi_plan_s *p) {
   std::vector<Inst *> one{&p->inst};
   int parts = 0;
   std::vector<BlockEnt> tab = build_table(one, 0, &parts);
+  // three partial-sum arrays: the outer-step kernels', and one per parity
+  // of the inner CG passes
+  p->inst.part_stride = parts;
+  p->inst.cg_inline = p->inst.nblocks <= kInlineMaxBlocks ? 1 : 0;
   hipError_t e = hipMalloc((void **)&p->d_tab, tab.size() * sizeof(BlockEnt));
-  if (e == hipSuccess) e = hipMalloc((void **)&p->d_part, (size_t)std::max(parts, 1) * 4 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void **)&p->d_part, (size_t)std::max(parts, 1) * 3 * 4 * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(p->d_tab, tab.data(), tab.size() * sizeof(BlockEnt), hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     p->ntab = (int)tab.size();
@@ -537,6 +541,7 @@ extern "C" pi_status pi_plan(int ndim, const int64_t dims[3], const double spaci
   set_walk(in, ndim, p->dims, 0, 0);
   in.gen = (mask || p->cc) ? 0 : 1;  // the cell-centred kernels always read codes
   in.inner_op = p->fixed_point ? 1 : 0;
+  in.bicg = p->bicgstab ? 1 : 0;
   // relative r.r at which the variant's CG has reached the precision of its
   // vectors (about a relative residual of 1e-7 in FP32, 1e-13 in FP64)
   in.inner_floor = p->fixed_point ? (p->fp64 ? 1e-26 : 1e-14) : 0.0;

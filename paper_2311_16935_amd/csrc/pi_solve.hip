@@ -38,9 +38,12 @@ struct Launcher {
   State *sts = nullptr;
   double *part = nullptr;
   int count = 0;             // instances
+  bool cg_finalize = false;  // some instance's CG passes need the finalize kernel
   Group grp[kShapes];
 
-  // the kernel over every instance, then (if it reduces) its finalize
+  // the kernel over every instance, then (if it reduces) its finalize; the
+  // CG passes of instances of at most kInlineMaxBlocks blocks sum the
+  // previous pass's partials themselves and need none
   hipError_t go(KernelId k, hipStream_t s, int iarg = 0, const void *x = nullptr, void *y = nullptr,
                 bool finalize = true) const {
     for (int g = 0; g < kShapes; ++g) {
@@ -49,7 +52,8 @@ struct Launcher {
       hipError_t e = launch(k, fp64, g, la);
       if (e != hipSuccess) return e;
     }
-    if (finalize && reduces(k)) return launch_finalize(k, insts, sts, part, count, s);
+    if (k == K_CG_STEP && !cg_finalize) return hipSuccess;
+    if (finalize && reduces(k)) return launch_finalize(k, insts, sts, part, count, s, iarg);
     return hipSuccess;
   }
 
@@ -66,7 +70,7 @@ struct Launcher {
         } else {
           // one pass per CG iteration; each folds in the previous one's
           // update, and the outer kernel folds in the last one's
-          if ((e = go(K_CG_STEP, s)) != hipSuccess) return e;
+          if ((e = go(K_CG_STEP, s, i)) != hipSuccess) return e;
         }
       }
     }
@@ -99,6 +103,7 @@ State fresh_state() {
   s.first = 1;
   s.alpha = 1.0;
   s.omega = 1.0;
+  s.stop_at = kNoStop;
   return s;
 }
 
@@ -217,6 +222,7 @@ Launcher single_launcher(pi_plan_s *p) {
   L.sts = p->d_state;
   L.part = p->d_part;
   L.count = 1;
+  L.cg_finalize = !p->bicgstab && !p->inst.cg_inline;
   L.grp[shape_of(p->ndim, p->inst.vw, p->inst.gen, p->inst.cc)] = Group{p->d_tab, p->ntab};
   return L;
 }
@@ -263,6 +269,7 @@ struct BatchSetup {
   bool bicg = false;
   int inner = 1;
   int parts = 0;
+  bool cg_finalize = false;
   std::vector<Inst> host;
   std::vector<BlockEnt> tabs[kShapes];
 };
@@ -302,6 +309,12 @@ pi_status batch_setup(int64_t count, const pi_plan_t *plans, const void *const *
       if (e.inst >= 0) e.inst = (int32_t)idx[g][e.inst];
     b.parts = total;
   }
+  b.cg_finalize = false;
+  for (auto &h : b.host) {
+    h.part_stride = b.parts;
+    h.cg_inline = h.nblocks <= kInlineMaxBlocks ? 1 : 0;
+    if (!b.bicg && !h.cg_inline) b.cg_finalize = true;
+  }
   return PI_OK;
 }
 
@@ -330,6 +343,7 @@ extern "C" pi_status pi_solve_batched(int64_t count, const pi_plan_t *plans, con
   Launcher L;
   L.fp64 = b.fp64;
   L.count = (int)count;
+  L.cg_finalize = b.cg_finalize;
   hipStream_t cap = nullptr;
   hipGraphExec_t exec = nullptr;
   State *hst = nullptr;
@@ -337,7 +351,7 @@ extern "C" pi_status pi_solve_batched(int64_t count, const pi_plan_t *plans, con
   std::vector<State> init(count, fresh_state());
   if (hipMalloc((void **)&L.insts, count * sizeof(Inst)) != hipSuccess ||
       hipMalloc((void **)&L.sts, count * sizeof(State)) != hipSuccess ||
-      hipMalloc((void **)&L.part, (size_t)std::max(b.parts, 1) * 4 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void **)&L.part, (size_t)std::max(b.parts, 1) * 3 * 4 * sizeof(double)) != hipSuccess ||
       hipHostMalloc((void **)&hst, 2 * count * sizeof(State), hipHostMallocDefault) != hipSuccess) {
     rc = PI_ERR_OOM;
     goto done;
@@ -392,7 +406,7 @@ constexpr int64_t kNaTab = PI_NOALLOC_MAX_TABLE;
 constexpr size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 constexpr size_t kNaOffSts = align256(kNaInsts * sizeof(Inst));
 constexpr size_t kNaOffPart = kNaOffSts + align256(kNaInsts * sizeof(State));
-constexpr size_t kNaOffTab = kNaOffPart + align256(kNaParts * 4 * sizeof(double));
+constexpr size_t kNaOffTab = kNaOffPart + align256(kNaParts * 3 * 4 * sizeof(double));
 constexpr size_t kNaBytes = kNaOffTab + align256(kNaTab * sizeof(BlockEnt));
 
 }  // namespace
@@ -469,6 +483,7 @@ extern "C" pi_status pi_solve_batched_noalloc(int64_t count, const pi_plan_t *pl
   Launcher L;
   L.fp64 = b.fp64;
   L.count = (int)count;
+  L.cg_finalize = b.cg_finalize;
   L.insts = (Inst *)(base);
   L.sts = (State *)(base + kNaOffSts);
   L.part = (double *)(base + kNaOffPart);
@@ -545,28 +560,39 @@ extern "C" pi_status pi_time_kernel(pi_plan_t p, int kernel, int32_t reps, doubl
   in.inner_iters = 1 << 30;
   State st = fresh_state();
   st.first = 0;
-  st.have_delta = 1;
-  st.tail = 1;
-  st.inner = 2;  // a pass that reads and writes the correction
+  st.have_delta = 1;  // a correction is pending (CG: from every pass)
   st.dvalid = 1;
   st.rr = 1.0;
   st.alpha = 1e-3;
   st.beta = 0.5;
   st.normS2 = 1.0;
   const KernelId k = kernel == PI_K_OUTER ? K_OUTER : K_CG_STEP;
+  // CG pass 2 (reads and writes the correction) and the outer kernel read
+  // pass 1's partial sums: alpha = 1e-3 and beta = 1, finite and fixed
+  std::vector<double> slots((size_t)p->inst.nblocks * 4);
+  for (int i = 0; i < p->inst.nblocks; ++i) {
+    slots[4 * i + 0] = 1e3;  // p.q
+    slots[4 * i + 1] = 0.0;  // r.q
+    slots[4 * i + 2] = 0.0;  // q.q
+    slots[4 * i + 3] = 1.0;  // r.r
+  }
+  const int kpass = 2;
   hipEvent_t a = nullptr, b = nullptr;
   pi_status rc = PI_ERR_DEVICE;
   float ms = 0.f;
   if (hipMemcpyAsync(p->d_inst, &in, sizeof(Inst), hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(p->d_state, &st, sizeof(State), hipMemcpyHostToDevice, stream) != hipSuccess)
+      hipMemcpyAsync(p->d_state, &st, sizeof(State), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(p->d_part + (size_t)(1 + 1) * in.part_stride * 4 + (size_t)in.part_base * 4, slots.data(),
+                     slots.size() * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
     return PI_ERR_DEVICE;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) goto out;
   // the kernel alone: without its finalize the state, and so every launch,
   // stays the same
-  if (L.go(k, stream, 0, nullptr, nullptr, false) != hipSuccess) goto out;  // warm-up launch
+  if (L.go(k, stream, kpass, nullptr, nullptr, false) != hipSuccess) goto out;  // warm-up launch
   if (hipEventRecord(a, stream) != hipSuccess) goto out;
   for (int i = 0; i < reps; ++i)
-    if (L.go(k, stream, 0, nullptr, nullptr, false) != hipSuccess) goto out;
+    if (L.go(k, stream, kpass, nullptr, nullptr, false) != hipSuccess) goto out;
   if (hipEventRecord(b, stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
       hipEventElapsedTime(&ms, a, b) != hipSuccess)
     goto out;

@@ -391,3 +391,29 @@ def test_fixed_point_cg_variant_reaches_the_same_field(name, make, fp64):
     fast = plan.solve(g, tol=1e-6, max_iter=2000)
     assert fast.info["inner_iters_total"] < base.info["inner_iters_total"]
     plan.close()
+
+
+@pytest.mark.parametrize("fixed_point", [False, True], ids=["paper_iteration", "fixed_point_variant"])
+def test_many_block_grid_takes_alpha_and_beta_from_a_finalize_kernel(fixed_point):
+    """An instance of more than 2048 blocks (here 2113: 64 x 130 x 130 cells,
+    one cell per lane, two-plane segments) gets the CG scalars from a
+    finalize kernel after each pass instead of re-summing the partials in
+    every block; both routes must reach the oracle's fixed point."""
+    import paper_2311_16935_amd as pi
+    from oracle.solve import fixed_point_cg
+
+    announce("finalize route", fixed_point)
+    w = synth.random_small(71, 3, (64, 130, 130), anisotropic=False, mask_frac=0.0)
+    g = _grads(w, False)
+    plan = pi.Plan(w.dims, w.spacing, fixed_point=fixed_point)
+    pi.pi_set_tile(plan.handle, 2, 1)
+    waves = 1 * 130 * 65
+    assert (waves + 3) // 4 > 2048
+    res = plan.solve(g, tol=1e-9, max_iter=200000)
+    assert res.status == 0, res.info
+    sys_ = oracle_for(w)
+    ref = fixed_point_cg(sys_, sys_.source([np_(x).astype(np.float64) for x in g]), rtol=1e-13).P
+    err = rel_maxabs(np_(res.P).astype(np.float64).ravel(), ref)
+    print(f"finalize route: outer {res.info['outer_iters']}, inner {res.info['inner_iters_total']}, err {err:.2e}")
+    assert err <= 1e-5, err
+    plan.close()
