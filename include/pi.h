@@ -87,6 +87,7 @@ typedef struct pi_plan_s *pi_plan_t;
 
 /* pi_solve flags */
 #define PI_WARM_START 0x1u      /* P holds P^0 on entry (else P^0 = 0)            */
+#define PI_ASYNC 0x2u           /* enqueue the whole solve on the stream; see below */
 
 /* operators for pi_apply */
 #define PI_OP_M 0  /* [W^{n+1}] = I - W^{n+1}                                    */
@@ -101,6 +102,9 @@ typedef struct pi_info {
   double ms;                 /* wall time of the call, host clock, milliseconds */
   int32_t status;            /* pi_status of this instance                      */
   int32_t components;        /* connected groups of data cells                  */
+  int32_t worklist_rebuilds; /* batched calls: times the work list was shrunk
+                                to the unfinished instances (0 for pi_solve)   */
+  int32_t reserved;
 } pi_info;
 
 /*
@@ -179,16 +183,39 @@ int32_t pi_get_lane_cells(pi_plan_t plan);
  * together with PI_ERR_NOT_CONVERGED.
  * Errors: PI_ERR_INVALID_ARG, PI_ERR_NONFINITE, PI_ERR_NOT_CONVERGED,
  * PI_ERR_DIVERGED, PI_ERR_DEVICE.
+ *
+ * With PI_ASYNC the call only enqueues work on `stream` and returns PI_OK
+ * (or an argument/launch error) at once; `info` is not touched.  Algorithm
+ * 1's loop runs until eps_R <= tol, so its length is known only on the
+ * device, and without device-side graph conditionals the queue cannot stop
+ * itself: the call enqueues enough outer-step replays to reach max_iter
+ * (<= 2^22), every kernel of which returns at once after the stop, then the
+ * gauge and a copy of the final state.  A loose max_iter therefore costs
+ * about 0.3 ms of empty launches per 8 unneeded outer steps at 256^3.  After
+ * the stream has completed, P holds the result and pi_last_info gives its
+ * pi_info (ms = 0) and status.  Without PI_ASYNC the call returns once the
+ * solve is done: it polls the convergence flag between replays and never
+ * launches past the stop.
  */
 pi_status pi_solve(pi_plan_t plan, const void *gx, const void *gy, const void *gz, void *P,
                    double tol, int64_t max_iter, uint32_t flags, pi_info *info, void *stream);
 
 /*
+ * pi_last_info -- result of the plan's last pi_solve: fills info (ms = 0)
+ * and returns its status.  For a PI_ASYNC solve, valid once the stream it
+ * was enqueued on has completed.
+ */
+pi_status pi_last_info(pi_plan_t plan, pi_info *info);
+
+/*
  * pi_solve_batched -- many independent grids of uneven size in one set of
  * launches: every kernel of an outer step walks a work list of tiles drawn
- * from all still-active instances, scalars and the convergence flag are kept
- * per instance, converged instances drop out of the work list, and one outer
- * step is captured as a HIP graph and replayed.
+ * from the unfinished instances, scalars and the convergence flag are kept
+ * per instance, and a bundle of outer steps is captured as a HIP graph and
+ * replayed.  A finished instance's tiles return at once; when finished
+ * instances hold a quarter of the listed tiles, the host (between replays)
+ * rebuilds the work list without them and captures the graph again
+ * (pi_info.worklist_rebuilds counts this).
  *   count         number of instances (>= 1); plans[i] must be distinct and
  *                 share the precision flag.
  *   gx, gy, gz, P host arrays of `count` device pointers, as for pi_solve

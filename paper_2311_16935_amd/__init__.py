@@ -39,6 +39,7 @@ PI_INNER_BICGSTAB = 0x2
 PI_FIXED_POINT_CG = 0x4
 PI_CELL_CENTERED = 0x8
 PI_WARM_START = 0x1
+PI_ASYNC = 0x2
 PI_OP_M, PI_OP_N, PI_OP_L = 0, 1, 2
 
 
@@ -51,6 +52,8 @@ class PiInfo(ctypes.Structure):
         ("ms", ctypes.c_double),
         ("status", ctypes.c_int32),
         ("components", ctypes.c_int32),
+        ("worklist_rebuilds", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -80,6 +83,8 @@ def _load():
     lib.pi_solve_batched.restype = ctypes.c_int
     lib.pi_solve_batched_noalloc.argtypes = lib.pi_solve_batched.argtypes
     lib.pi_solve_batched_noalloc.restype = ctypes.c_int
+    lib.pi_last_info.argtypes = [vp, ctypes.POINTER(PiInfo)]
+    lib.pi_last_info.restype = ctypes.c_int
     lib.pi_source.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.pi_source.restype = ctypes.c_int
     lib.pi_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp]
@@ -102,7 +107,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("pi_plan", "pi_plan_destroy", "pi_workspace_bytes", "pi_set_inner_iters", "pi_set_tile",
-            "pi_get_tile", "pi_get_lane_cells", "pi_solve",
+            "pi_get_tile", "pi_get_lane_cells", "pi_solve", "pi_last_info",
             "pi_solve_batched", "pi_solve_batched_noalloc", "pi_source", "pi_apply", "pi_time_kernel", "pi_autotune", "pi_status_string")
 
 PI_K_OUTER, PI_K_INNER = 0, 1
@@ -191,6 +196,12 @@ def _batched(fn, plans, gx, gy, gz, P, tol, max_iter, flags, stream):
     return rc, list(infos)
 
 
+def pi_last_info(plan):
+    info = PiInfo()
+    rc = lib.pi_last_info(plan, ctypes.byref(info))
+    return rc, info
+
+
 def pi_solve_batched(plans, gx, gy, gz, P, tol, max_iter, flags=0, stream=None):
     return _batched(lib.pi_solve_batched, plans, gx, gy, gz, P, tol, max_iter, flags, stream)
 
@@ -273,6 +284,23 @@ class Plan:
             raise ValueError(f"{name} is required")
         if not t.is_cuda or t.dtype != self.dtype or tuple(t.shape) != self.shape or not t.is_contiguous():
             raise ValueError(f"{name} must be a contiguous {self.dtype} CUDA tensor of shape {self.shape}")
+
+    def solve_async(self, grads, P, tol=1e-6, max_iter=100000, warm_start=False, stream=None):
+        """Enqueue the whole solve on ``stream`` (PI_ASYNC); after the stream
+        has completed, ``last_info()`` gives its status and info."""
+        gz = grads[2] if self.ndim == 3 else None
+        for i, g in enumerate(grads[: self.ndim]):
+            self._check(g, f"grad[{i}]")
+        self._check(P, "P")
+        flags = PI_ASYNC | (PI_WARM_START if warm_start else 0)
+        rc, _ = pi_solve(self.handle, grads[0], grads[1], gz, P, tol, max_iter, flags, stream)
+        if rc != PI_OK:
+            raise PiError(rc, "pi_solve (async)")
+        return P
+
+    def last_info(self):
+        rc, info = pi_last_info(self.handle)
+        return rc, info.as_dict()
 
     def solve(self, grads, P=None, tol=1e-6, max_iter=10**7, warm_start=False, stream=None, check=True):
         gx, gy = grads[0], grads[1]

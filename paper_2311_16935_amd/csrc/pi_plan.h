@@ -67,7 +67,10 @@ void set_walk(Inst &in, int ndim, const int64_t dims[3], int mseg_override, int 
 // Single-instance table and partial slots of a plan.
 hipError_t plan_tables(pi_plan_s *p);
 
-// Block table of a set of instances (all of one ndim), XCD-aware.
-std::vector<BlockEnt> build_table(const std::vector<Inst *> &insts, int part_base0, int *part_total);
+// Block table of a set of instances, XCD-aware.  With assign_parts the
+// instances' partial-sum slots are numbered from part_base0 on (else their
+// part_base is kept: a table rebuilt for a subset of a batch).
+std::vector<BlockEnt> build_table(const std::vector<Inst *> &insts, int part_base0, int *part_total,
+                                  bool assign_parts = true);
 
 }  // namespace pi

@@ -340,12 +340,13 @@ void set_walk(Inst &in, int ndim, const int64_t dims[3], int mseg_override, int 
   in.nblocks = (int32_t)((in.nwaves + kWavesPerBlock - 1) / kWavesPerBlock);
 }
 
-std::vector<BlockEnt> build_table(const std::vector<Inst *> &insts, int part_base0, int *part_total) {
+std::vector<BlockEnt> build_table(const std::vector<Inst *> &insts, int part_base0, int *part_total,
+                                  bool assign_parts) {
   std::vector<std::vector<BlockEnt>> q(kXcd);
   int base = part_base0;
   for (size_t i = 0; i < insts.size(); ++i) {
     Inst *in = insts[i];
-    in->part_base = base;
+    if (assign_parts) in->part_base = base;
     base += in->nblocks;
     const int B = in->nblocks;
     for (int k = 0; k < kXcd; ++k) {

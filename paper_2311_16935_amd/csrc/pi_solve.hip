@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <array>
 #include <chrono>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -26,6 +27,7 @@ using namespace pi;
 namespace {
 
 constexpr int kUnroll = 8;  // outer steps per graph replay
+constexpr int64_t kAsyncMaxIter = 1 << 22;  // bound on max_iter of PI_ASYNC solves
 
 struct Group {               // instances of one launch shape (shape_of)
   BlockEnt *tab = nullptr;   // device
@@ -108,9 +110,15 @@ State fresh_state() {
 }
 
 // Replay the outer-step graph until every instance reports done.  `hstate`
-// is a pinned buffer of 2 * count records.
+// is a pinned buffer of 2 * count records.  Each poll checks a snapshot of
+// the states while the next replays run.  If `rebuild` is given and returns
+// true for a snapshot in which some instance is still running, the loop
+// stops there (*stopped = true) so that the caller can shrink the work list;
+// `launched` counts replays across such restarts against max_iter.
 pi_status iterate(hipGraphExec_t exec, hipStream_t stream, State *dstate, State *hstate, int64_t count,
-                  int64_t max_iter, int unroll) {
+                  int64_t max_iter, int unroll, int64_t *launched,
+                  const std::function<bool(const State *)> &rebuild = nullptr, bool *stopped = nullptr) {
+  if (stopped) *stopped = false;
   hipEvent_t ev[2];
   if (hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess) return PI_ERR_DEVICE;
   if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
@@ -119,42 +127,48 @@ pi_status iterate(hipGraphExec_t exec, hipStream_t stream, State *dstate, State 
   }
   // every replay advances each unfinished instance by `unroll` outer steps
   const int64_t bound = max_iter / unroll + 4;
-  int64_t launched = 0;
   int replays = 1;
   int cur = 0;
   bool pending = false;
   pi_status rc = PI_ERR_DEVICE;
   const size_t bytes = (size_t)count * sizeof(State);
+  auto all_done = [&](const State *snap) {
+    for (int64_t i = 0; i < count; ++i)
+      if (!snap[i].done) return false;
+    return true;
+  };
   for (;;) {
-    const int r = (int)std::min<int64_t>(replays, bound - launched);
+    const int r = (int)std::min<int64_t>(replays, bound - *launched);
     for (int i = 0; i < r; ++i)
       if (hipGraphLaunch(exec, stream) != hipSuccess) goto out;
-    launched += r;
+    *launched += r;
     if (hipMemcpyAsync(hstate + cur * count, dstate, bytes, hipMemcpyDeviceToHost, stream) != hipSuccess) goto out;
     if (hipEventRecord(ev[cur], stream) != hipSuccess) goto out;
     if (pending) {
       // check the previous snapshot while the latest replays run
-      const int prev = cur ^ 1;
-      if (hipEventSynchronize(ev[prev]) != hipSuccess) goto out;
-      bool all = true;
-      for (int64_t i = 0; i < count && all; ++i) all = hstate[prev * count + i].done != 0;
-      if (all) {
+      const State *snap = hstate + (cur ^ 1) * count;
+      if (hipEventSynchronize(ev[cur ^ 1]) != hipSuccess) goto out;
+      if (all_done(snap)) {
+        rc = PI_OK;
+        break;
+      }
+      if (rebuild && rebuild(snap)) {
+        if (stopped) *stopped = true;
         rc = PI_OK;
         break;
       }
     }
     pending = true;
     cur ^= 1;
-    if (launched >= bound) {
+    if (*launched >= bound) {
       if (hipEventSynchronize(ev[cur ^ 1]) != hipSuccess) goto out;
-      bool all = true;
-      for (int64_t i = 0; i < count && all; ++i) all = hstate[(cur ^ 1) * count + i].done != 0;
-      rc = all ? PI_OK : PI_ERR_DEVICE;
+      rc = all_done(hstate + (cur ^ 1) * count) ? PI_OK : PI_ERR_DEVICE;
       break;
     }
     replays = std::min(replays * 2, 16);
   }
 out:
+  // the events of the replays still in flight are ordered on `stream`
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   return rc;
@@ -179,6 +193,7 @@ void fill_info(pi_info *info, const State &s, const pi_plan_s *p, double ms) {
   info->ms = ms;
   info->status = s.status;
   info->components = p->ncomp;
+  info->worklist_rebuilds = 0;
 }
 
 int worst(int a, int b) {
@@ -232,8 +247,12 @@ Launcher single_launcher(pi_plan_s *p) {
 extern "C" pi_status pi_solve(pi_plan_t p, const void *gx, const void *gy, const void *gz, void *P, double tol,
                               int64_t max_iter, uint32_t flags, pi_info *info, void *stream_) {
   const auto t0 = std::chrono::steady_clock::now();
-  if (!p || (flags & ~PI_WARM_START)) return PI_ERR_INVALID_ARG;
+  if (!p || (flags & ~(PI_WARM_START | PI_ASYNC))) return PI_ERR_INVALID_ARG;
   if (!has_table(p)) return PI_ERR_OOM;
+  const bool async = (flags & PI_ASYNC) != 0;
+  // the asynchronous form enqueues one replay per `unroll` outer steps up
+  // to max_iter: it needs a bound the caller can afford
+  if (async && max_iter > kAsyncMaxIter) return PI_ERR_INVALID_ARG;
   hipStream_t stream = (hipStream_t)stream_;
   Inst in = p->inst;
   if (!set_user(in, p, gx, gy, gz, P, tol, max_iter, flags)) return PI_ERR_INVALID_ARG;
@@ -251,12 +270,35 @@ extern "C" pi_status pi_solve(pi_plan_t p, const void *gx, const void *gy, const
     if (capture(L, cap_stream(p), p->inner_iters, p->bicgstab, &p->graph) != hipSuccess) return PI_ERR_DEVICE;
     p->graph_key = key;
   }
+  if (async) {
+    // enough replays to reach max_iter outer steps (each replay advances an
+    // unfinished instance by `unroll`; after the stop every kernel of a
+    // replay returns at once), then the gauge and a copy of the final state
+    // into the plan's pinned record, all on `stream`
+    const int unroll = unroll_for(p->inner_iters);
+    const int64_t reps = (max_iter + 1 + unroll - 1) / unroll;
+    for (int64_t r = 0; r < reps; ++r)
+      if (hipGraphLaunch(p->graph, stream) != hipSuccess) return PI_ERR_DEVICE;
+    if (L.go(K_GAUGE_SUM, stream) != hipSuccess || L.go(K_GAUGE_GROUPS, stream) != hipSuccess ||
+        L.go(K_GAUGE_APPLY, stream) != hipSuccess ||
+        hipMemcpyAsync(p->h_state, p->d_state, sizeof(State), hipMemcpyDeviceToHost, stream) != hipSuccess)
+      return PI_ERR_DEVICE;
+    return PI_OK;
+  }
   // h_state holds three records: [0] final snapshot, [1..2] polling buffers
-  pi_status rc = iterate(p->graph, stream, p->d_state, p->h_state + 1, 1, max_iter, unroll_for(p->inner_iters));
+  int64_t launched = 0;
+  pi_status rc =
+      iterate(p->graph, stream, p->d_state, p->h_state + 1, 1, max_iter, unroll_for(p->inner_iters), &launched);
   if (rc != PI_OK) return rc;
   rc = finish(L, stream, p->d_state, p->h_state, 1);
   if (rc != PI_OK) return rc;
   fill_info(info, *p->h_state, p, ms_since(t0));
+  return (pi_status)p->h_state->status;
+}
+
+extern "C" pi_status pi_last_info(pi_plan_t p, pi_info *info) {
+  if (!p || !info) return PI_ERR_INVALID_ARG;
+  fill_info(info, *p->h_state, p, 0.0);
   return (pi_status)p->h_state->status;
 }
 
@@ -271,8 +313,65 @@ struct BatchSetup {
   int parts = 0;
   bool cg_finalize = false;
   std::vector<Inst> host;
+  std::vector<int64_t> idx[kShapes];  // batch index of the instances of each launch shape
   std::vector<BlockEnt> tabs[kShapes];
+
+  // block table of launch shape g holding only the instances marked live
+  // (their partial-sum slots unchanged)
+  std::vector<BlockEnt> live_table(int g, const std::vector<char> &live) {
+    std::vector<Inst *> sub;
+    std::vector<int64_t> id;
+    for (int64_t i : idx[g])
+      if (live[i]) {
+        sub.push_back(&host[i]);
+        id.push_back(i);
+      }
+    if (sub.empty()) return {};
+    int unused = 0;
+    std::vector<BlockEnt> t = build_table(sub, 0, &unused, false);
+    for (auto &e : t)
+      if (e.inst >= 0) e.inst = (int32_t)id[e.inst];
+    return t;
+  }
 };
+
+// Between replay bundles the work list drops finished instances once they
+// hold a quarter of the listed blocks: their blocks would only read the done
+// flag and exit.
+struct WorkList {
+  std::vector<char> live;
+  int64_t listed = 0;  // blocks in the current tables
+  int rebuilds = 0;
+
+  explicit WorkList(const BatchSetup &b) : live(b.host.size(), 1) {
+    for (const auto &h : b.host) listed += h.nblocks;
+  }
+  // from a snapshot of the states: shrink now?
+  bool shrink(const BatchSetup &b, const State *snap) {
+    int64_t running = 0;
+    for (size_t i = 0; i < b.host.size(); ++i)
+      if (!snap[i].done) running += b.host[i].nblocks;
+    if (running > listed * 3 / 4) return false;
+    for (size_t i = 0; i < b.host.size(); ++i) live[i] = snap[i].done ? 0 : 1;
+    listed = running;
+    ++rebuilds;
+    return true;
+  }
+};
+
+// Write the live instances' tables over the launcher's (each no longer than
+// before) on `stream`.
+hipError_t upload_live_tables(BatchSetup &b, const WorkList &wl, Launcher &L, hipStream_t stream) {
+  for (int g = 0; g < kShapes; ++g) {
+    if (L.grp[g].ntab <= 0) continue;
+    b.tabs[g] = b.live_table(g, wl.live);
+    L.grp[g].ntab = (int)b.tabs[g].size();
+    if (!b.tabs[g].empty() && hipMemcpyAsync(L.grp[g].tab, b.tabs[g].data(), b.tabs[g].size() * sizeof(BlockEnt),
+                                             hipMemcpyHostToDevice, stream) != hipSuccess)
+      return hipErrorUnknown;
+  }
+  return hipStreamSynchronize(stream);
+}
 
 pi_status batch_setup(int64_t count, const pi_plan_t *plans, const void *const *gx, const void *const *gy,
                       const void *const *gz, void *const *P, const double *tol, int64_t max_iter, uint32_t flags,
@@ -292,12 +391,11 @@ pi_status batch_setup(int64_t count, const pi_plan_t *plans, const void *const *
     b.inner = std::max(b.inner, p->inner_iters);
   }
   std::vector<Inst *> by[kShapes];
-  std::vector<int64_t> idx[kShapes];
   for (int64_t i = 0; i < count; ++i) {
     const Inst &h = b.host[i];
     const int g = shape_of(h.ndim, h.vw, h.gen, h.cc);
     by[g].push_back(&b.host[i]);
-    idx[g].push_back(i);
+    b.idx[g].push_back(i);
   }
   b.parts = 0;
   for (int g = 0; g < kShapes; ++g) {
@@ -306,7 +404,7 @@ pi_status batch_setup(int64_t count, const pi_plan_t *plans, const void *const *
     b.tabs[g] = build_table(by[g], b.parts, &total);
     // the table names instances by position inside the group; map to batch index
     for (auto &e : b.tabs[g])
-      if (e.inst >= 0) e.inst = (int32_t)idx[g][e.inst];
+      if (e.inst >= 0) e.inst = (int32_t)b.idx[g][e.inst];
     b.parts = total;
   }
   b.cg_finalize = false;
@@ -319,11 +417,12 @@ pi_status batch_setup(int64_t count, const pi_plan_t *plans, const void *const *
 }
 
 pi_status batch_report(int64_t count, const pi_plan_t *plans, const State *hst, pi_info *infos,
-                       std::chrono::steady_clock::time_point t0) {
+                       std::chrono::steady_clock::time_point t0, int rebuilds) {
   const double ms = ms_since(t0);
   int w = PI_OK;
   for (int64_t i = 0; i < count; ++i) {
     fill_info(infos ? infos + i : nullptr, hst[i], plans[i], ms);
+    if (infos) infos[i].worklist_rebuilds = rebuilds;
     w = worst(w, hst[i].status);
   }
   return (pi_status)w;
@@ -373,12 +472,47 @@ extern "C" pi_status pi_solve_batched(int64_t count, const pi_plan_t *plans, con
   if (L.go(K_INIT, stream, (flags & PI_WARM_START) ? 1 : 0) != hipSuccess || L.go(K_SOURCE, stream) != hipSuccess)
     goto done;
   if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) goto done;
-  if (capture(L, cap, b.inner, b.bicg, &exec) != hipSuccess) goto done;
-  rc = iterate(exec, stream, L.sts, hst, count, max_iter, unroll_for(b.inner));
-  if (rc != PI_OK) goto done;
-  rc = finish(L, stream, L.sts, hst, count);
-  if (rc != PI_OK) goto done;
-  rc = batch_report(count, plans, hst, infos, t0);
+  {
+    WorkList wl(b);
+    int64_t launched = 0;
+    auto shrink = [&](const State *snap) { return wl.shrink(b, snap); };
+    for (;;) {
+      if (capture(L, cap, b.inner, b.bicg, &exec) != hipSuccess) {
+        rc = PI_ERR_DEVICE;
+        goto done;
+      }
+      bool stopped = false;
+      rc = iterate(exec, stream, L.sts, hst, count, max_iter, unroll_for(b.inner), &launched, shrink, &stopped);
+      if (rc != PI_OK) goto done;
+      if (!stopped) break;
+      // the replays still in flight finish before the tables change
+      if (hipStreamSynchronize(stream) != hipSuccess) {
+        rc = PI_ERR_DEVICE;
+        goto done;
+      }
+      (void)hipGraphExecDestroy(exec);
+      exec = nullptr;
+      if (upload_live_tables(b, wl, L, stream) != hipSuccess) {
+        rc = PI_ERR_DEVICE;
+        goto done;
+      }
+    }
+    // the gauge runs over every instance
+    for (int g = 0; g < kShapes; ++g) {
+      if (b.idx[g].empty()) continue;
+      std::vector<char> all(count, 1);
+      b.tabs[g] = b.live_table(g, all);
+      L.grp[g].ntab = (int)b.tabs[g].size();
+      if (hipMemcpyAsync(L.grp[g].tab, b.tabs[g].data(), b.tabs[g].size() * sizeof(BlockEnt), hipMemcpyHostToDevice,
+                         stream) != hipSuccess) {
+        rc = PI_ERR_DEVICE;
+        goto done;
+      }
+    }
+    rc = finish(L, stream, L.sts, hst, count);
+    if (rc != PI_OK) goto done;
+    rc = batch_report(count, plans, hst, infos, t0, wl.rebuilds);
+  }
 done:
   if (exec) (void)hipGraphExecDestroy(exec);
   if (cap) (void)hipStreamDestroy(cap);
@@ -443,22 +577,41 @@ hipError_t noalloc_scratch(unsigned char **out) {
 
 // Replays of the outer-step sequence without a graph: the launches go
 // straight onto the stream; the done flags are copied back to pageable host
-// memory and checked every `unroll` outer steps.
-pi_status noalloc_iterate(const Launcher &L, hipStream_t stream, int64_t count, int64_t max_iter, int inner,
-                          bool bicg) {
-  const int unroll = unroll_for(inner);
+// memory and checked every `unroll` outer steps, and the work list shrinks
+// as in pi_solve_batched (the tables are rewritten in place).
+pi_status noalloc_iterate(BatchSetup &b, Launcher &L, hipStream_t stream, int64_t count, int64_t max_iter,
+                          int *rebuilds) {
+  const int unroll = unroll_for(b.inner);
   const int64_t bound = max_iter / unroll + 4;
   const size_t bytes = (size_t)count * sizeof(State);
+  WorkList wl(b);
+  pi_status rc = PI_ERR_DEVICE;
   for (int64_t r = 0; r < bound; ++r) {
-    if (L.outer_steps(stream, unroll, inner, bicg) != hipSuccess) return PI_ERR_DEVICE;
+    if (L.outer_steps(stream, unroll, b.inner, b.bicg) != hipSuccess) return PI_ERR_DEVICE;
     if (hipMemcpyAsync(g_na_host, L.sts, bytes, hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
       return PI_ERR_DEVICE;
     bool all = true;
     for (int64_t i = 0; i < count && all; ++i) all = g_na_host[i].done != 0;
-    if (all) return PI_OK;
+    if (all) {
+      rc = PI_OK;
+      break;
+    }
+    if (wl.shrink(b, g_na_host) && upload_live_tables(b, wl, L, stream) != hipSuccess) return PI_ERR_DEVICE;
   }
-  return PI_ERR_DEVICE;
+  *rebuilds = wl.rebuilds;
+  if (rc != PI_OK) return rc;
+  // the gauge runs over every instance
+  std::vector<char> all(count, 1);
+  for (int g = 0; g < kShapes; ++g) {
+    if (b.idx[g].empty()) continue;
+    b.tabs[g] = b.live_table(g, all);
+    L.grp[g].ntab = (int)b.tabs[g].size();
+    if (hipMemcpyAsync(L.grp[g].tab, b.tabs[g].data(), b.tabs[g].size() * sizeof(BlockEnt), hipMemcpyHostToDevice,
+                       stream) != hipSuccess)
+      return PI_ERR_DEVICE;
+  }
+  return PI_OK;
 }
 
 }  // namespace
@@ -506,9 +659,10 @@ extern "C" pi_status pi_solve_batched_noalloc(int64_t count, const pi_plan_t *pl
     return PI_ERR_DEVICE;
   if (L.go(K_INIT, stream, (flags & PI_WARM_START) ? 1 : 0) != hipSuccess || L.go(K_SOURCE, stream) != hipSuccess)
     return PI_ERR_DEVICE;
-  rc = noalloc_iterate(L, stream, count, max_iter, b.inner, b.bicg);
+  int rebuilds = 0;
+  rc = noalloc_iterate(b, L, stream, count, max_iter, &rebuilds);
   if (rc == PI_OK) rc = finish(L, stream, L.sts, g_na_host, count);
-  if (rc == PI_OK) rc = batch_report(count, plans, g_na_host, infos, t0);
+  if (rc == PI_OK) rc = batch_report(count, plans, g_na_host, infos, t0, rebuilds);
   (void)hipStreamSynchronize(stream);
   return rc;
 }

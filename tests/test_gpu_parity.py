@@ -268,6 +268,59 @@ def test_batched_matches_single_solves():
             p.close()
 
 
+def test_batched_work_list_drops_finished_instances():
+    """A large instance that finishes early (zero source, or a loose
+    tolerance) leaves the batched work list: the call rebuilds its tables
+    without it, and the instance still running returns exactly what its own
+    solve returns."""
+    import paper_2311_16935_amd as pi
+
+    announce("batched work list")
+    big = synth.random_small(35, 2, (256, 256), mask_frac=0.0)
+    small = synth.random_small(36, 3, (24, 17, 13), mask_frac=0.1)
+    plans = [_plan(big, False), _plan(small, False)]
+    grads = [_grads(big, False), _grads(small, False)]
+    single = plans[1].solve(grads[1], tol=1e-9, max_iter=100000)
+    for g0, tol0 in (([torch.zeros_like(x) for x in grads[0]], 1e-6), (grads[0], 0.3)):
+        rc, Ps, infos = pi.solve_batched(plans, [g0, grads[1]], tol=[tol0, 1e-9], max_iter=100000)
+        assert rc == 0, infos
+        assert infos[0]["outer_iters"] < infos[1]["outer_iters"]
+        assert infos[1]["worklist_rebuilds"] >= 1, infos
+        assert infos[1]["outer_iters"] == single.info["outer_iters"]
+        assert torch.equal(torch.nan_to_num(Ps[1], nan=7.0), torch.nan_to_num(single.P, nan=7.0))
+        # the early instance was gauged and returned like any other
+        lone = plans[0].solve(g0, tol=tol0, max_iter=100000)
+        assert torch.equal(Ps[0], lone.P)
+    for p in plans:
+        p.close()
+
+
+def test_async_solve_matches_the_blocking_one():
+    """PI_ASYNC enqueues the solve on the stream and returns at once; after
+    a stream sync, P and pi_last_info match the blocking solve exactly, also
+    when max_iter stops it first."""
+    import paper_2311_16935_amd as pi
+
+    announce("async solve")
+    w = synth.random_small(37, 3, (40, 22, 31), mask_frac=0.05)
+    for fp64 in (False, True):
+        plan = _plan(w, fp64)
+        g = _grads(w, fp64)
+        for tol, max_iter in ((1e-8, 100000), (1e-12, 40)):
+            ref = plan.solve(g, tol=tol, max_iter=max_iter, check=False)
+            P = torch.full_like(ref.P, 3.0)
+            stream = torch.cuda.current_stream()
+            plan.solve_async(g, P, tol=tol, max_iter=max_iter, stream=stream)
+            stream.synchronize()
+            rc, info = plan.last_info()
+            assert rc == ref.status, (rc, ref.status)
+            for k in ("outer_iters", "inner_iters_total", "eps_R", "eps_P", "status"):
+                assert info[k] == ref.info[k], k
+            assert torch.equal(torch.nan_to_num(P, nan=7.0), torch.nan_to_num(ref.P, nan=7.0))
+        assert ref.status == pi.PI_ERR_NOT_CONVERGED and ref.info["outer_iters"] == 40
+        plan.close()
+
+
 def test_sin64_config():
     # 64^2, unit spacing, P = sin(2 pi x) cos(2 pi y) with 5 % gradient noise,
     # FP64, solved to eps_R <= 1e-10; against the oracle's Algorithm 1 (exact
