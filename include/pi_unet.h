@@ -44,16 +44,19 @@ typedef struct pu_tensor {
 } pu_tensor;
 
 /*
- * pu_conv -- y[o(p), co] = act(sum_t sum_ci x[g_t(p), ci] w[t][ci][co] + b[co])
+ * pu_conv -- y[o(p), co] = act(sum_t sum_ci x[g_t(p), ci] w[t][co][ci] + b[co])
  * over the positions p of an (md, mh, mw) grid per sample, with
  * g_t(p) = p * sin + offs[t] (zero outside x) and o(p) = p * sout + oo.
- *   3x3x3 convolution:           taps 27, offsets {-1,0,1}^3, sin = sout = 1
- *   its data gradient:           per-tap transposed weights, negated offsets
+ *   3x3x3 convolution:           taps 27, offsets {-1,0,1}^3, sin = sout = 1,
+ *                                weights [t][cout][cin] (per-tap transposed
+ *                                from the layer's [t][cin][cout])
+ *   its data gradient:           the layer's [t][cin][cout] weights as
+ *                                [t][N = cin][K = cout], negated offsets
  *   2x2x2 stride-2 transposed conv (one output parity oo): taps 1, sout = 2
  *   its data gradient:           taps 8, offsets {0,1}^3, sin = 2
  * offs: host array of 3 * taps int8 offsets (dz, dy, dx) per tap, copied
- * into the launch.  w: BF16 [taps][cin][cout] device array, 16-byte aligned,
- * with cout = y->c a multiple of 8; bias: FP32 [cout] or NULL; relu: 0/1;
+ * into the launch.  w: BF16 [taps][cout][cin] device array (K = cin
+ * contiguous), 16-byte aligned; bias: FP32 [cout] or NULL; relu: 0/1;
  * y_fp32: 1 stores FP32 (y->ptr is float*), else BF16.  accumulate: 1 adds
  * into y instead of overwriting it.
  */

@@ -3,12 +3,12 @@
 // layers around them.
 //
 // Every convolution-like layer is one implicit GEMM
-//     Y[o(p), co] = sum_t sum_ci X[g_t(p), ci] W[t][ci][co]
+//     Y[o(p), co] = sum_t sum_ci X[g_t(p), ci] W[t][co][ci]
 // over positions p: M = positions, N = output channels, K = taps x input
-// channels.  A workgroup of four waves computes a 64 x 64 output tile; each
-// K step stages a 64 x 32 slab of X and a 32 x 64 slab of W in LDS and every
-// wave issues v_mfma_f32_16x16x32_bf16 for its 16 rows and four 16-column
-// subtiles.  Operand lane layout of that instruction (lane l = 0..63,
+// channels, both operands K-contiguous (activations channels-last, weights
+// [tap][cout][cin]), so every slab is staged with 16-byte loads and stores.
+// A workgroup of four waves computes a 128 x 64 (or 256 x 32) output tile
+// with v_mfma_f32_16x16x32_bf16, double-buffering its K slabs in LDS.  Operand lane layout of that instruction (lane l = 0..63,
 // element e = 0..7): A[l % 16][8 (l / 16) + e], B[8 (l / 16) + e][l % 16];
 // result element e of lane l is D[4 (l / 16) + e][l % 16].
 #include <hip/hip_runtime.h>
@@ -79,89 +79,128 @@ __device__ inline bf16x8 lds8(const uint16_t *p) { return __builtin_bit_cast(bf1
 
 constexpr int kLdsRow = 40;  // 32 K values + 8 padding, 80-byte rows
 
-// Y = act(X * W + b) over one 64-position x 64-channel tile
+// Y = act(X * W + b) over one BM-position x BN-channel tile, W given as
+// [tap][cout][cin] so that both operands are K-contiguous in memory and in
+// LDS.  Four waves; wave w computes rows [w BM/4, (w+1) BM/4) of the tile as
+// (BM/64) x (BN/16) blocks of 16 x 16 (eight MFMAs per K step of 32 for
+// both tile shapes: 128 x 64 for layers of 64 or more output channels,
+// 256 x 32 for 32).  The K loop runs over (tap, 32-channel slab) steps with
+// two LDS buffers: the global loads of step s + 1 are in flight while the
+// MFMAs of step s run, then land in the other buffer; one barrier per step.
+template <int BN>
 __global__ __launch_bounds__(256) void k_conv(ConvP a) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[64][kLdsRow];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[64][kLdsRow];
+  constexpr int BM = 8192 / BN;          // 128 or 256 positions
+  constexpr int RA = BM / 64;            // A rows staged per thread (16-byte chunks)
+  constexpr int MI = BM / 64;            // 16-row blocks per wave
+  constexpr int NJ = BN / 16;            // 16-column blocks
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][BM][kLdsRow];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN][kLdsRow];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t p0 = (int64_t)blockIdx.x * 64;
-  const int n0 = blockIdx.y * 64;
-  // A staging role: row r, eight K values from kq
-  const int r = tid >> 2, kq = (tid & 3) * 8;
-  const int64_t p = p0 + r;
-  const bool pin = p < a.P;
-  int nb = 0, mz = 0, my = 0, mx = 0;
-  if (pin) decompose(p, a.md, a.mh, a.mw, nb, mz, my, mx);
-  // B staging role: K row kb, eight channels from nq
-  const int kb = tid >> 3, nq = (tid & 7) * 8;
-  const bool xvec = (a.x.ld % 8 == 0) && (a.x.off % 8 == 0) && (a.cin % 8 == 0);
-  f4 acc[4];
+  const int64_t p0 = (int64_t)blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+  // A staging: rows tid/4 + 64 i, eight K values from kq
+  const int kq = (tid & 3) * 8;
+  int rz[RA], ry[RA], rx[RA], rb[RA];
+  bool rin[RA];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int t = 0; t < a.taps; ++t) {
-    const int iz = mz * a.sin + a.offs[t][0], iy = my * a.sin + a.offs[t][1], ix = mx * a.sin + a.offs[t][2];
-    const bool v = pin && iz >= 0 && iz < a.x.d && iy >= 0 && iy < a.x.h && ix >= 0 && ix < a.x.w;
-    const int64_t xb = v ? ((((int64_t)nb * a.x.d + iz) * a.x.h + iy) * a.x.w + ix) * a.x.ld + a.x.off : 0;
-    const uint16_t *wt = a.w + (int64_t)t * a.cin * a.cout;
-    for (int k0 = 0; k0 < a.cin; k0 += 32) {
-      uint4 av = {0u, 0u, 0u, 0u};
-      if (v && k0 + kq < a.cin) {
+  for (int i = 0; i < RA; ++i) {
+    const int64_t p = p0 + (tid >> 2) + 64 * i;
+    rin[i] = p < a.P;
+    rb[i] = rz[i] = ry[i] = rx[i] = 0;
+    if (rin[i]) decompose(p, a.md, a.mh, a.mw, rb[i], rz[i], ry[i], rx[i]);
+  }
+  // B staging: channel row tid/4 (BN rows, all threads when BN = 64), eight K values from kq
+  const int brow = tid >> 2;
+  const bool bact = brow < BN;
+  const bool xvec = (a.x.ld % 8 == 0) && (a.x.off % 8 == 0) && (a.cin % 8 == 0);
+  const bool wvec = a.cin % 8 == 0;
+  const int ksteps = (a.cin + 31) / 32;
+  const int S = a.taps * ksteps;
+  uint4 ra[RA], rbv;
+  auto fetch = [&](int step) {
+    const int t = step / ksteps, k0 = (step % ksteps) * 32 + kq;
+#pragma unroll
+    for (int i = 0; i < RA; ++i) {
+      ra[i] = uint4{0u, 0u, 0u, 0u};
+      const int iz = rz[i] * a.sin + a.offs[t][0], iy = ry[i] * a.sin + a.offs[t][1],
+                ix = rx[i] * a.sin + a.offs[t][2];
+      const bool v = rin[i] && iz >= 0 && iz < a.x.d && iy >= 0 && iy < a.x.h && ix >= 0 && ix < a.x.w && k0 < a.cin;
+      if (v) {
+        const int64_t xb = ((((int64_t)rb[i] * a.x.d + iz) * a.x.h + iy) * a.x.w + ix) * a.x.ld + a.x.off + k0;
         if (xvec) {
-          av = *(const uint4 *)(a.x.p + xb + k0 + kq);
+          ra[i] = *(const uint4 *)(a.x.p + xb);
         } else {
           uint16_t tmp[8];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) tmp[e] = (k0 + kq + e < a.cin) ? a.x.p[xb + k0 + kq + e] : (uint16_t)0;
-          av = *(const uint4 *)tmp;
+          for (int e = 0; e < 8; ++e) tmp[e] = (k0 + e < a.cin) ? a.x.p[xb + e] : (uint16_t)0;
+          ra[i] = *(const uint4 *)tmp;
         }
       }
-      *(uint4 *)&As[r][kq] = av;
-      uint16_t bv[8];
-      if (k0 + kb < a.cin && n0 + nq + 8 <= a.cout) {
-        const uint4 b4 = *(const uint4 *)(wt + (int64_t)(k0 + kb) * a.cout + n0 + nq);
-        *(uint4 *)bv = b4;
+    }
+    rbv = uint4{0u, 0u, 0u, 0u};
+    if (bact && n0 + brow < a.cout && k0 < a.cin) {
+      const uint16_t *wr = a.w + ((int64_t)t * a.cout + n0 + brow) * a.cin + k0;
+      if (wvec) {
+        rbv = *(const uint4 *)wr;
       } else {
+        uint16_t tmp[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-          bv[e] = (k0 + kb < a.cin && n0 + nq + e < a.cout) ? wt[(int64_t)(k0 + kb) * a.cout + n0 + nq + e]
-                                                            : (uint16_t)0;
+        for (int e = 0; e < 8; ++e) tmp[e] = (k0 + e < a.cin) ? wr[e] : (uint16_t)0;
+        rbv = *(const uint4 *)tmp;
       }
+    }
+  };
+  auto stash = [&](int buf) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) Bs[nq + e][kb] = bv[e];
-      __syncthreads();
-      const bf16x8 av8 = lds8(&As[16 * wave + (lane & 15)][8 * (lane >> 4)]);
+    for (int i = 0; i < RA; ++i) *(uint4 *)&As[buf][(tid >> 2) + 64 * i][kq] = ra[i];
+    if (bact) *(uint4 *)&Bs[buf][brow][kq] = rbv;
+  };
+  f4 acc[MI][NJ];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if (n0 + 16 * j < a.cout) {
-          const bf16x8 bv8 = lds8(&Bs[16 * j + (lane & 15)][8 * (lane >> 4)]);
-          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av8, bv8, acc[j], 0, 0, 0);
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int s = 0; s < S; ++s) {
+    const int cur = s & 1;
+    if (s + 1 < S) fetch(s + 1);
+    bf16x8 bv[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) bv[j] = lds8(&Bs[cur][16 * j + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+    for (int i = 0; i < MI; ++i) {
+      const bf16x8 av = lds8(&As[cur][wave * (BM / 4) + 16 * i + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (s + 1 < S) stash(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = wave * (BM / 4) + 16 * i + 4 * (lane >> 4) + e, col = 16 * j + (lane & 15);
+        const int64_t pp = p0 + row;
+        const int co = n0 + col;
+        if (pp >= a.P || co >= a.cout) continue;
+        int b2, z2, y2, x2;
+        decompose(pp, a.md, a.mh, a.mw, b2, z2, y2, x2);
+        const int oz = z2 * a.sout + a.ooz, oy = y2 * a.sout + a.ooy, ox = x2 * a.sout + a.oox;
+        const int64_t yi = ((((int64_t)b2 * a.y.d + oz) * a.y.h + oy) * a.y.w + ox) * a.y.ld + a.y.off + co;
+        float val = acc[i][j][e] + (a.bias ? a.bias[co] : 0.f);
+        if (a.relu) val = fmaxf(val, 0.f);
+        if (a.yfp32) {
+          float *yf = (float *)a.y.p;
+          yf[yi] = a.acc ? yf[yi] + val : val;
+        } else {
+          a.y.p[yi] = f2bf(a.acc ? bf2f(a.y.p[yi]) + val : val);
         }
       }
-      __syncthreads();
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int row = 16 * wave + 4 * (lane >> 4) + e, col = 16 * j + (lane & 15);
-      const int64_t pp = p0 + row;
-      const int co = n0 + col;
-      if (pp >= a.P || co >= a.cout) continue;
-      int b2, z2, y2, x2;
-      decompose(pp, a.md, a.mh, a.mw, b2, z2, y2, x2);
-      const int oz = z2 * a.sout + a.ooz, oy = y2 * a.sout + a.ooy, ox = x2 * a.sout + a.oox;
-      const int64_t yi = ((((int64_t)b2 * a.y.d + oz) * a.y.h + oy) * a.y.w + ox) * a.y.ld + a.y.off + co;
-      float val = acc[j][e] + (a.bias ? a.bias[co] : 0.f);
-      if (a.relu) val = fmaxf(val, 0.f);
-      if (a.yfp32) {
-        float *yf = (float *)a.y.p;
-        yf[yi] = a.acc ? yf[yi] + val : val;
-      } else {
-        a.y.p[yi] = f2bf(a.acc ? bf2f(a.y.p[yi]) + val : val);
-      }
-    }
-  }
 }
 
 struct WgP {
@@ -554,7 +593,6 @@ extern "C" pi_status pu_conv(const pu_tensor *x, const void *w, int32_t taps, co
   if ((md - 1) * sout + oo[0] >= y->d || (mh - 1) * sout + oo[1] >= y->h || (mw - 1) * sout + oo[2] >= y->w ||
       oo[0] < 0 || oo[1] < 0 || oo[2] < 0)
     return PI_ERR_INVALID_ARG;
-  if (y->c % 8 != 0) return PI_ERR_INVALID_ARG;  // weight rows are read eight channels at a time
   ConvP a;
   a.x = tens(x);
   a.y = tens(y);
@@ -577,8 +615,12 @@ extern "C" pi_status pu_conv(const pu_tensor *x, const void *w, int32_t taps, co
   a.P = (int64_t)x->n * md * mh * mw;
   for (int t = 0; t < taps; ++t)
     for (int k = 0; k < 3; ++k) a.offs[t][k] = offs[3 * t + k];
-  const dim3 grid(blocks(a.P, 64), (a.cout + 63) / 64);
-  k_conv<<<grid, dim3(256), 0, (hipStream_t)stream>>>(a);
+  // 32 output channels: a 256 x 32 tile wastes no MFMA columns
+  if (a.cout <= 32) {
+    k_conv<32><<<dim3(blocks(a.P, 256), 1), dim3(256), 0, (hipStream_t)stream>>>(a);
+  } else {
+    k_conv<64><<<dim3(blocks(a.P, 128), (a.cout + 63) / 64), dim3(256), 0, (hipStream_t)stream>>>(a);
+  }
   return PU_LAUNCHED;
 }
 

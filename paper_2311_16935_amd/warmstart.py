@@ -210,7 +210,8 @@ class UNet:
 
     # ------------------------------------------------------------------ layers
     def _conv(self, name, x, y, m, relu=True, stream=None):
-        U.pu_conv(x, self.w(name), 27, TAPS3, self.b(name), y, m, 1, 1, (0, 0, 0), relu, False, False, stream)
+        U.pu_conv(x, self.w(name, self.wt), 27, TAPS3, self.b(name), y, m, 1, 1, (0, 0, 0), relu, False, False,
+                  stream)
 
     def _conv_back(self, name, x, g, gx, m, B, stream=None):
         """g holds dL/d(pre-activation) of layer `name` with input x: writes its
@@ -219,7 +220,7 @@ class UNet:
         U.pu_conv_wgrad(x, g, 27, TAPS3, self.w(name, self.grad), self.b(name, self.grad), m, 1, 1, (0, 0, 0),
                         B["work"], stream)
         if gx is not None:
-            U.pu_conv(g, self.w(name, self.wt), 27, NEG3, None, gx, m, 1, 1, (0, 0, 0), False, False, False, stream)
+            U.pu_conv(g, self.w(name), 27, NEG3, None, gx, m, 1, 1, (0, 0, 0), False, False, False, stream)
 
     def forward(self, B, stream=None):
         T = U.tensor
@@ -234,7 +235,7 @@ class UNet:
         for l in reversed(range(top)):
             src = T(B["bot"]) if l == top - 1 else T(B[f"ub{l + 1}"])
             L = self.layers[f"up{l}"]
-            w = self.w(L.name)
+            w = self.w(L.name, self.wt)
             for q, oo in enumerate(UP8):
                 U.pu_conv(src, w[q * L.cin * L.cout:], 1, ZERO1, None, T(B[f"cat{l}"], 0, self.ch[l]), R[l + 1], 1,
                           2, oo, False, False, False, stream)
@@ -258,7 +259,7 @@ class UNet:
             src, gsrc = ("bot", "gbot") if l == top - 1 else (f"ub{l + 1}", f"gub{l + 1}")
             L = self.layers[f"up{l}"]
             gup = T(B[f"gcat{l}"], 0, self.ch[l])
-            U.pu_conv(gup, self.w(L.name, self.wt), 8, UP8, None, T(B[gsrc]), R[l + 1], 2, 1, (0, 0, 0), False,
+            U.pu_conv(gup, self.w(L.name), 8, UP8, None, T(B[gsrc]), R[l + 1], 2, 1, (0, 0, 0), False,
                       False, False, stream)
             gw = self.w(L.name, self.grad)
             for q, oo in enumerate(UP8):

@@ -71,7 +71,7 @@ def test_conv3_forward(cin, cout, xoff, yoff):
     W = _bf(rng.normal(size=(27, cin, cout)) / math.sqrt(27 * cin))
     b = rng.normal(size=cout).astype(np.float32).astype(np.float64)
     xd = _dev_bf(_wide(x, xoff, 16))
-    wd, bd = _dev_bf(W), _dev_f(b)
+    wd, bd = _dev_bf(W.transpose(0, 2, 1)), _dev_f(b)  # [tap][cout][cin]
     for relu in (False, True):
         ref = O.conv3(x, W, b, relu=relu)
         y = torch.zeros(shape + (cout + 16,), dtype=torch.bfloat16, device=DEV)
@@ -105,10 +105,10 @@ def test_conv3_backward(cin, cout):
     U.pu_transpose_taps(wd, wt, 27, cin, cout)
     same = bool(torch.equal(wt.cpu(), wd.cpu().permute(0, 2, 1).contiguous()))
     assert same, 'per-tap transpose differs'
-    if cin % 8 == 0:
-        gx = torch.zeros(shape + (cin,), dtype=torch.float32, device=DEV)
-        U.pu_conv(U.tensor(gyd), wt, 27, NEG3, None, U.tensor(gx), shape[1:], y_fp32=True)
-        _check(_host(gx), rgx, False, "dgrad")
+    # data gradient: the layer's [tap][cin][cout] weights are [tap][N = cin][K = cout]
+    gx = torch.zeros(shape + (cin,), dtype=torch.float32, device=DEV)
+    U.pu_conv(U.tensor(gyd), wd, 27, NEG3, None, U.tensor(gx), shape[1:], y_fp32=True)
+    _check(_host(gx), rgx, False, "dgrad")
     npos = math.prod(shape)
     work = torch.zeros(U.pu_wgrad_work_floats(27, cin, cout, npos), dtype=torch.float32, device=DEV)
     dW = torch.zeros((27, cin, cout), dtype=torch.float32, device=DEV)
@@ -155,13 +155,13 @@ def test_upconv_forward_backward():
     rgx, rgW, _ = O.upconv_backward(x, W, gy)
     xd, wd, gyd = _dev_bf(x), _dev_bf(W), _dev_bf(gy)
     y = torch.zeros(fine + (cout,), dtype=torch.float32, device=DEV)
-    for q, oo in enumerate(UP8):
-        U.pu_conv(U.tensor(xd), wd[q], 1, [(0, 0, 0)], None, U.tensor(y), shape[1:], 1, 2, oo, y_fp32=True)
-    _check(_host(y), ref, False, "upconv fwd")
     wt = torch.empty((8, cout, cin), dtype=torch.bfloat16, device=DEV)
     U.pu_transpose_taps(wd, wt, 8, cin, cout)
+    for q, oo in enumerate(UP8):
+        U.pu_conv(U.tensor(xd), wt[q], 1, [(0, 0, 0)], None, U.tensor(y), shape[1:], 1, 2, oo, y_fp32=True)
+    _check(_host(y), ref, False, "upconv fwd")
     gx = torch.zeros(shape + (cin,), dtype=torch.float32, device=DEV)
-    U.pu_conv(U.tensor(gyd), wt, 8, UP8, None, U.tensor(gx), shape[1:], 2, 1, (0, 0, 0), y_fp32=True)
+    U.pu_conv(U.tensor(gyd), wd, 8, UP8, None, U.tensor(gx), shape[1:], 2, 1, (0, 0, 0), y_fp32=True)
     _check(_host(gx), rgx, False, "upconv dgrad")
     work = torch.zeros(U.pu_wgrad_work_floats(1, cin, cout, math.prod(shape)), dtype=torch.float32, device=DEV)
     dW = torch.zeros((8, cin, cout), dtype=torch.float32, device=DEV)
