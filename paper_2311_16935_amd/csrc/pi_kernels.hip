@@ -856,8 +856,8 @@ __device__ inline T apply_l(const T *a, uint32_t cd, int bits, T vC, T vW, T vE,
 //   p_k = r_k + beta_k p_{k-1},            q_k = A p_k,
 // with A = [W^{n+1}] (or the fixed point's operator for the variant).  The
 // stencil needs p_k at the neighbours, so r, q and p are read there and
-// written to the other buffer of each pair (pass k reads buffer k & 1; the
-// outer kernel writes the residual into res, buffer 0).  Reductions: p.q,
+// written to the other buffer of each pair.  Pass 0 has p_0 = r_0 (the
+// outer residual): it reads r alone and writes p and q.  Reductions: p.q,
 // r.q, q.q, r.r into partial array 1 + (k & 1).  alpha_{k-1} and beta_k come
 // from pass k-1's sums (cg_scalars): every block adds them up itself, or,
 // for instances of many blocks, a finalize kernel did so into the state.
@@ -901,9 +901,13 @@ __device__ inline CgPass<T> cg_pass(const Inst &in, State *st, const double *par
       be = st->beta;
     }
   }
+  // buffers: pass 0 reads the outer residual (res) only, since p_0 = r_0,
+  // and writes p and q; pass k >= 1 reads r from res/res1 by the parity of
+  // k + 1 and writes the other, reads q and p by the parity of k and writes
+  // the other
   const int o = k & 1;
-  c.rold = gp<T>(o ? in.res1 : in.res);
-  c.rnew = gp<T>(o ? in.res : in.res1);
+  c.rold = gp<T>(k == 0 || o ? in.res : in.res1);
+  c.rnew = gp<T>(o ? in.res1 : in.res);
   c.qold = gp<T>(o ? in.q1 : in.q);
   c.qnew = gp<T>(o ? in.q : in.q1);
   c.pold = gp<T>(in.p[o]);
@@ -921,9 +925,9 @@ __device__ inline double *cg_part(const Inst &in, double *part, int k) {
   return part + (int64_t)(1 + (k & 1)) * in.part_stride * 4;
 }
 
-template <typename T, int ND, int W, bool GEN>
-__global__ __launch_bounds__(kBlock) void k_cg_step(const BlockEnt *tab, const Inst *insts, State *sts,
-                                                    double *part, int kpass) {
+template <typename T, int ND, int W, bool GEN, bool FIRST>
+__device__ __forceinline__ void cg_step_body(const BlockEnt *tab, const Inst *insts, State *sts, double *part,
+                                             int kpass) {
   PI_PROLOGUE
   const CgPass<T> cg = cg_pass<T>(in, st, part, e.lb, kpass);
   if (cg.skip) return;
@@ -988,8 +992,45 @@ __global__ __launch_bounds__(kBlock) void k_cg_step(const BlockEnt *tab, const I
     stv<W>(cg.rnew, c, rv);
     if (cg.wr_d) stv<W>(cg.d, c, dv);
   };
-  march<ND, W, GEN, T, Aux, Out>(wk, load, load1, aux, body, store);
+  if constexpr (FIRST) {
+    // p_0 = r_0: only the residual is read; p and q are written
+    auto load0 = [&](int64_t c) { return ldv<W>(cg.rold, c); };
+    auto load01 = [&](int64_t c) -> T { return cg.rold[c]; };
+    auto aux0 = [&](int64_t c) {
+      const Vec<T, W> r = ldv<W>(cg.rold, c);
+      Vec<Aux, W> x;
+#pragma unroll
+      for (int k = 0; k < W; ++k) x.e[k] = Aux{r.e[k], T(0)};
+      return x;
+    };
+    auto store0 = [&](int64_t c, const Out (&o)[W]) {
+      Vec<T, W> pv, qv;
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        pv.e[k] = o[k].p;
+        qv.e[k] = o[k].q;
+      }
+      stv<W>(cg.pnew, c, pv);
+      stv<W>(cg.qnew, c, qv);
+    };
+    march<ND, W, GEN, T, Aux, Out>(wk, load0, load01, aux0, body, store0);
+  } else {
+    march<ND, W, GEN, T, Aux, Out>(wk, load, load1, aux, body, store);
+  }
   publish<4>(in, cg_part(in, part, kpass), e.lb, acc);
+}
+
+// pass 0 of an outer step and the passes after it, compiled apart so that
+// each gets its own register allocation
+template <typename T, int ND, int W, bool GEN>
+__global__ __launch_bounds__(kBlock) void k_cg_first(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                     double *part, int kpass) {
+  cg_step_body<T, ND, W, GEN, true>(tab, insts, sts, part, kpass);
+}
+template <typename T, int ND, int W, bool GEN>
+__global__ __launch_bounds__(kBlock) void k_cg_step(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                    double *part, int kpass) {
+  cg_step_body<T, ND, W, GEN, false>(tab, insts, sts, part, kpass);
 }
 
 // ---------------------------------------------------------------------------
@@ -1690,9 +1731,9 @@ __global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const 
 
 // One inner CG iteration with the previous one's update folded in, as
 // k_cg_step, for the cell-centred scheme.
-template <typename T, int W>
-__global__ __launch_bounds__(kBlock) void k_cg_step_cc(const BlockEnt *tab, const Inst *insts, State *sts,
-                                                      double *part, int kpass) {
+template <typename T, int W, bool FIRST>
+__device__ __forceinline__ void cg_step_cc_body(const BlockEnt *tab, const Inst *insts, State *sts, double *part,
+                                                int kpass) {
   PI_PROLOGUE
   const CgPass<T> cg = cg_pass<T>(in, st, part, e.lb, kpass);
   if (cg.skip) return;
@@ -1765,8 +1806,43 @@ __global__ __launch_bounds__(kBlock) void k_cg_step_cc(const BlockEnt *tab, cons
     stv<W>(cg.rnew, c, rv);
     if (cg.wr_d) stv<W>(cg.d, c, dv);
   };
-  march_cc<W, T, Aux, Out>(wk, load, load1, aux, body, store);
+  if constexpr (FIRST) {
+    // p_0 = r_0: only the residual is read; p and q are written
+    auto load0 = [&](int64_t c) { return ldv<W>(cg.rold, c); };
+    auto load01 = [&](int64_t o) -> T { return cg.rold[o]; };
+    auto aux0 = [&](int64_t c) {
+      const Vec<T, W> r = ldv<W>(cg.rold, c);
+      Vec<Aux, W> x;
+#pragma unroll
+      for (int k = 0; k < W; ++k) x.e[k] = Aux{r.e[k], T(0)};
+      return x;
+    };
+    auto store0 = [&](int64_t c, const Out (&o)[W]) {
+      Vec<T, W> pv, qv;
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        pv.e[k] = o[k].p;
+        qv.e[k] = o[k].q;
+      }
+      stv<W>(cg.pnew, c, pv);
+      stv<W>(cg.qnew, c, qv);
+    };
+    march_cc<W, T, Aux, Out>(wk, load0, load01, aux0, body, store0);
+  } else {
+    march_cc<W, T, Aux, Out>(wk, load, load1, aux, body, store);
+  }
   publish<4>(in, cg_part(in, part, kpass), e.lb, acc);
+}
+
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_cg_first_cc(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                       double *part, int kpass) {
+  cg_step_cc_body<T, W, true>(tab, insts, sts, part, kpass);
+}
+template <typename T, int W>
+__global__ __launch_bounds__(kBlock) void k_cg_step_cc(const BlockEnt *tab, const Inst *insts, State *sts,
+                                                      double *part, int kpass) {
+  cg_step_cc_body<T, W, false>(tab, insts, sts, part, kpass);
 }
 
 // y = M x, N x or (M - N) x for pi_apply
@@ -1857,7 +1933,10 @@ static hipError_t launch_t(KernelId k, int shape, const LaunchArgs &la) {
       else k_source<T, 2><<<grid, block, 0, s>>>(PI_ARGS);
       break;
     case K_OUTER: PI_MARCH(k_outer, PI_ARGS); break;
-    case K_CG_STEP: PI_MARCH(k_cg_step, PI_ARGS, la.iarg); break;
+    case K_CG_STEP:
+      if (la.iarg == 0) PI_MARCH(k_cg_first, PI_ARGS, la.iarg);
+      else PI_MARCH(k_cg_step, PI_ARGS, la.iarg);
+      break;
     case K_BICG_P:
       if (shape == kShapeCC || shape == kShapeCC4) return hipErrorInvalidValue;  // CG only
       PI_MARCH8(k_bicg_spmv_p, PI_ARGS);
