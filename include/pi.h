@@ -148,9 +148,11 @@ pi_status pi_set_inner_iters(pi_plan_t plan, int32_t iters);
  * Tile shape of the stencil kernels: every wave owns a strip of 64 *
  * lane_cells consecutive cells along x and marches `mseg` planes (3-D) or
  * rows (2-D) along the slowest axis.  mseg 0 restores the size-based
- * default.  lane_cells is 1 or 4 (4 needs nx % 4 == 0: each lane then moves
- * its cells with 16-byte accesses), 0 picks 4 when allowed, else 1.  The
- * autotuner sweeps both knobs.  Returns PI_ERR_INVALID_ARG for other values.
+ * default.  lane_cells is 1, 2 or 4 (4 needs nx % 4 == 0: each lane then
+ * moves its cells with 16-byte accesses; 2 needs an even nx and the
+ * face-crossing scheme: twice the waves of 4 at the same segment length),
+ * 0 picks 4 when allowed, else 1.  The autotuner sweeps both knobs.
+ * Returns PI_ERR_INVALID_ARG for other values.
  * Rebuilds the plan's block table (synchronous): PI_ERR_OOM if that fails,
  * and then pi_solve, pi_source, pi_apply and pi_time_kernel on the plan
  * return PI_ERR_OOM until a later pi_set_tile succeeds.
@@ -270,9 +272,9 @@ pi_status pi_source(pi_plan_t plan, const void *gx, const void *gy, const void *
  * pi_apply -- y = op x for op in {PI_OP_M, PI_OP_N, PI_OP_L} (the operators
  * of Eq. MatrixEquation), x and y device arrays of nx*ny*nz elements of the
  * plan's type; entries of x in masked cells are ignored, y is 0 there.
- * x and y must not overlap and must be 16-byte aligned when the plan moves
- * four cells per lane (pi_get_lane_cells == 4; torch allocations are), else
- * PI_ERR_INVALID_ARG.  Runs at the plan's current tile (pi_set_tile); the
+ * x and y must not overlap and must be aligned to the plan's lane access
+ * (16 bytes for four cells per lane, 8 or 16 for two; torch allocations
+ * are), else PI_ERR_INVALID_ARG.  Runs at the plan's current tile (pi_set_tile); the
  * result does not depend on it, the speed does: the tile the solve's
  * autotuner picks may give the apply too few waves, so a caller that applies
  * often can set its own.  Asynchronous.

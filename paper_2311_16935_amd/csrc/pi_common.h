@@ -28,23 +28,23 @@ constexpr int kXcd = 8;
 constexpr uint32_t kValidBit = 1u << 31;
 constexpr int kStates = 20;      // per-direction counter states (3-D uses 0..18)
 constexpr int kSegCells = 65536; // gauge segment length (cells)
-constexpr int kShapes = 10;      // stencil launch shapes: (2-D, 3-D) x (1, 4 cells per lane) x (codes read,
-                                 // derived), and the 2-D cell-centred scheme with 1 or 4 cells per lane
-constexpr int kShapeCC = 8;
+constexpr int kShapes = 14;      // stencil launch shapes: (2-D, 3-D) x (1, 4, 2 cells per lane) x (codes
+                                 // read, derived), and the 2-D cell-centred scheme with 1 or 4 cells per lane
+constexpr int kShapeCC = 12;
 // An instance of at most this many blocks runs its inner CG passes without a
 // finalize kernel: every block of a pass re-sums the previous pass's partial
 // sums (a few KB from L2) to get alpha and beta.  Larger instances keep the
 // finalize, which bounds those redundant reads.
 constexpr int kInlineMaxBlocks = 2048;
 constexpr int32_t kNoStop = 1 << 30;
-constexpr int kShapeCC4 = 9;
+constexpr int kShapeCC4 = 13;
 
-// Launch shape of an instance: bit 0 = 3-D, bit 1 = four cells per lane,
-// bit 2 = no mask (counter codes derived from cell coordinates); the
-// cell-centred scheme has a shape of its own.
+// Launch shape of an instance: (3-D) + 2 * (lane width: 0 for one cell, 1
+// for four, 2 for two) + 6 * (no mask: counter codes derived from cell
+// coordinates); the cell-centred scheme has shapes of its own.
 __host__ __device__ inline int shape_of(int ndim, int vw, int gen, int cc) {
   if (cc) return vw == 4 ? kShapeCC4 : kShapeCC;
-  return (ndim == 3 ? 1 : 0) | (vw == 4 ? 2 : 0) | (gen ? 4 : 0);
+  return (ndim == 3 ? 1 : 0) + 2 * (vw == 4 ? 1 : vw == 2 ? 2 : 0) + (gen ? 6 : 0);
 }
 
 // Cell-centred scheme: the 8 neighbours J (E, W, N, S, NE, NW, SE, SW) and
@@ -109,7 +109,7 @@ struct Inst {
   int32_t ndim;
   int32_t nx, ny, nz;
   int64_t ncell;
-  int32_t vw;       // cells per lane along x in stencil kernels (1 or 4)
+  int32_t vw;       // cells per lane along x in stencil kernels (1, 2 or 4)
   int32_t gen;      // 1: every cell holds data, codes follow from coordinates
   int32_t nxs;      // strips of 64 * vw cells along x
   int32_t rows;     // strips stacked along y: ny in 3-D, 1 in 2-D

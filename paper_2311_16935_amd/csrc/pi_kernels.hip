@@ -41,8 +41,8 @@ __device__ inline const PI_G T *gp(const void *p) {
 }
 
 // ---------------------------------------------------------------------------
-// short vectors: W consecutive cells of one array, moved with 16-byte
-// accesses (the caller guarantees 16-byte alignment when W * sizeof(T) >= 16)
+// short vectors: W consecutive cells of one array, moved with 16-byte (or,
+// for two FP32 cells, 8-byte) accesses; the caller guarantees the alignment
 // ---------------------------------------------------------------------------
 template <typename V, int W>
 struct Vec {
@@ -50,11 +50,15 @@ struct Vec {
 };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 template <int W, typename T>
 __device__ inline Vec<T, W> ldv(const PI_G T *p, int64_t c) {
   Vec<T, W> v;
-  if constexpr (W * sizeof(T) < 16) {
+  if constexpr (W > 1 && W * sizeof(T) == 8) {
+    const u32x2 u = *(const PI_G u32x2 *)(p + c);
+    memcpy(&v.e[0], &u, 8);
+  } else if constexpr (W * sizeof(T) < 16) {
 #pragma unroll
     for (int k = 0; k < W; ++k) v.e[k] = p[c + k];
   } else {
@@ -70,7 +74,11 @@ __device__ inline Vec<T, W> ldv(const PI_G T *p, int64_t c) {
 
 template <int W, typename T>
 __device__ inline void stv(PI_G T *p, int64_t c, const Vec<T, W> &v) {
-  if constexpr (W * sizeof(T) < 16) {
+  if constexpr (W > 1 && W * sizeof(T) == 8) {
+    u32x2 u;
+    memcpy(&u, &v.e[0], 8);
+    *(PI_G u32x2 *)(p + c) = u;
+  } else if constexpr (W * sizeof(T) < 16) {
 #pragma unroll
     for (int k = 0; k < W; ++k) p[c + k] = v.e[k];
   } else {
@@ -1893,7 +1901,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_cc(const BlockEnt *tab, const 
 // ---------------------------------------------------------------------------
 #define PI_ARGS tab, insts, sts, part
 
-// stencil kernels come in eight shapes (see shape_of)
+// stencil kernels come in twelve shapes (see shape_of)
 #define PI_MARCH8(KERN, ...)                                                              \
   do {                                                                                    \
     switch (shape) {                                                                      \
@@ -1901,10 +1909,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_cc(const BlockEnt *tab, const 
       case 1: KERN<T, 3, 1, false><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
       case 2: KERN<T, 2, 4, false><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
       case 3: KERN<T, 3, 4, false><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
-      case 4: KERN<T, 2, 1, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;             \
-      case 5: KERN<T, 3, 1, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;             \
-      case 6: KERN<T, 2, 4, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;             \
-      default: KERN<T, 3, 4, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
+      case 4: KERN<T, 2, 2, false><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
+      case 5: KERN<T, 3, 2, false><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
+      case 6: KERN<T, 2, 1, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;             \
+      case 7: KERN<T, 3, 1, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;             \
+      case 8: KERN<T, 2, 4, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;             \
+      case 9: KERN<T, 3, 4, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;             \
+      case 10: KERN<T, 2, 2, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
+      default: KERN<T, 3, 2, true><<<grid, block, 0, s>>>(__VA_ARGS__); break;            \
     }                                                                                     \
   } while (0)
 
@@ -1918,7 +1930,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_cc(const BlockEnt *tab, const 
 
 template <typename T>
 static hipError_t launch_t(KernelId k, int shape, const LaunchArgs &la) {
-  const int ndim = (shape == kShapeCC || shape == kShapeCC4) ? 2 : (shape & 1) ? 3 : 2;
+  const int ndim = (shape == kShapeCC || shape == kShapeCC4) ? 2 : (shape % 2) ? 3 : 2;
   const dim3 grid(la.nblocks), block(kBlock);
   const BlockEnt *tab = la.tab;
   const Inst *insts = la.insts;

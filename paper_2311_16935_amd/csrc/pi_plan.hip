@@ -307,9 +307,11 @@ void set_walk(Inst &in, int ndim, const int64_t dims[3], int mseg_override, int 
   in.ny = (int32_t)dims[1];
   in.nz = ndim == 3 ? (int32_t)dims[2] : 1;
   in.ncell = (int64_t)in.nx * in.ny * in.nz;
-  // four cells per lane (16-byte accesses) need rows that start 16-byte aligned
-  const bool can4 = in.nx % 4 == 0;
-  in.vw = vw_override == 1 ? 1 : (can4 ? 4 : 1);
+  // four (two) cells per lane, 16-byte (8-byte) accesses, need rows that
+  // start aligned to them; the default is the widest allowed (two only for
+  // the face-crossing scheme), the measured order at every size tried
+  const bool can4 = in.nx % 4 == 0, can2 = in.nx % 2 == 0 && !in.cc;
+  in.vw = vw_override == 1 ? 1 : vw_override == 2 ? 2 : (can4 ? 4 : can2 ? 2 : 1);
   const int strip = kWave * in.vw;
   in.nxs = (in.nx + strip - 1) / strip;
   int64_t strips;
@@ -683,8 +685,11 @@ extern "C" void pi_plan_destroy(pi_plan_t p) {
 extern "C" size_t pi_workspace_bytes(pi_plan_t p) { return p ? p->bytes : 0; }
 
 extern "C" pi_status pi_set_tile(pi_plan_t p, int32_t mseg, int32_t lane_cells) {
-  if (!p || mseg < 0 || (lane_cells != 0 && lane_cells != 1 && lane_cells != 4)) return PI_ERR_INVALID_ARG;
+  if (!p || mseg < 0 || (lane_cells != 0 && lane_cells != 1 && lane_cells != 2 && lane_cells != 4))
+    return PI_ERR_INVALID_ARG;
   if (lane_cells == 4 && p->dims[0] % 4 != 0) return PI_ERR_INVALID_ARG;
+  // two cells per lane: face-crossing plans with an even row length
+  if (lane_cells == 2 && (p->dims[0] % 2 != 0 || p->cc)) return PI_ERR_INVALID_ARG;
   // the captured outer-step graph holds the old table: drop it first, so
   // that no failure below leaves it pointing at freed memory
   if (p->graph) (void)hipGraphExecDestroy(p->graph);

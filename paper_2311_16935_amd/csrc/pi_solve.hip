@@ -690,7 +690,9 @@ extern "C" pi_status pi_source(pi_plan_t p, const void *gx, const void *gy, cons
 extern "C" pi_status pi_apply(pi_plan_t p, int op, const void *x, void *y, void *stream_) {
   if (!p || !x || !y || op < PI_OP_M || op > PI_OP_L || x == y) return PI_ERR_INVALID_ARG;
   // four cells per lane move 16-byte vectors
-  if (p->inst.vw == 4 && (((uintptr_t)x | (uintptr_t)y) & 15u) != 0) return PI_ERR_INVALID_ARG;
+  const size_t vbytes = (size_t)p->inst.vw * (p->fp64 ? 8 : 4);
+  if (p->inst.vw > 1 && (((uintptr_t)x | (uintptr_t)y) & (std::min<size_t>(vbytes, 16) - 1)) != 0)
+    return PI_ERR_INVALID_ARG;
   if (!has_table(p)) return PI_ERR_OOM;
   hipStream_t stream = (hipStream_t)stream_;
   // the operator reads only plan fields of the device instance record, which
@@ -776,8 +778,10 @@ extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, v
   pi_status rc;
   if (best[0] < 0) {
     std::vector<std::array<int32_t, 2>> cand;
-    const std::vector<int32_t> widths =
-        p->dims[0] % 4 == 0 ? std::vector<int32_t>{4, 1} : std::vector<int32_t>{1};
+    std::vector<int32_t> widths;
+    if (p->dims[0] % 4 == 0) widths.push_back(4);
+    if (p->dims[0] % 2 == 0 && !p->cc) widths.push_back(2);
+    widths.push_back(1);
     for (int32_t vw : widths) {
       if ((rc = pi_set_tile(p, 0, vw)) != PI_OK) return rc;
       cand.push_back({p->inst.mseg, vw});

@@ -351,7 +351,7 @@ def test_sin64_config():
 def test_derived_codes_and_lane_widths_match_stored_codes(ndim, dims):
     """A plan without a mask derives the counter codes from cell coordinates;
     with an all-ones mask it reads the stored codes.  Every operator apply
-    must agree bitwise between the two, and between 1 and 4 cells per lane."""
+    must agree bitwise between the two, and between 1, 2 and 4 cells per lane."""
     import paper_2311_16935_amd as pi
 
     announce("codes/lanes", dims)
@@ -364,7 +364,7 @@ def test_derived_codes_and_lane_widths_match_stored_codes(ndim, dims):
     for op in (pi.PI_OP_M, pi.PI_OP_N, pi.PI_OP_L):
         outs = []
         for plan in (gen, stored):
-            for lanes in (1, 4):
+            for lanes in (1, 2, 4):
                 pi.pi_set_tile(plan.handle, 3, lanes)
                 assert pi.pi_get_lane_cells(plan.handle) == lanes
                 outs.append(plan.apply(op, x).cpu())
@@ -372,12 +372,17 @@ def test_derived_codes_and_lane_widths_match_stored_codes(ndim, dims):
             assert torch.equal(o, outs[0]), op
     # the solve reads the same codes: identical trajectories at equal tiles
     g = [t.to(DEV, torch.float32) for t in w.grads]
-    pi.pi_set_tile(gen.handle, 0, 4)
-    pi.pi_set_tile(stored.handle, 0, 4)
-    a = gen.solve(g, tol=1e-9, max_iter=100000)
-    b = stored.solve(g, tol=1e-9, max_iter=100000)
-    assert a.info["outer_iters"] == b.info["outer_iters"]
-    assert torch.equal(a.P.cpu(), b.P.cpu())
+    sys_ = oracle_for(w)
+    ref = fixed_point(sys_, sys_.source([np_(x).astype(np.float64) for x in g]))
+    for lanes in (4, 2):
+        pi.pi_set_tile(gen.handle, 0, lanes)
+        pi.pi_set_tile(stored.handle, 0, lanes)
+        a = gen.solve(g, tol=1e-9, max_iter=100000)
+        b = stored.solve(g, tol=1e-9, max_iter=100000)
+        assert a.info["outer_iters"] == b.info["outer_iters"]
+        assert torch.equal(a.P.cpu(), b.P.cpu())
+        # and it reaches the oracle's fixed point with two cells per lane too
+        assert rel_maxabs(np_(a.P).astype(np.float64).ravel(), ref) <= 1e-5, lanes
     gen.close()
     stored.close()
 
