@@ -101,6 +101,14 @@ __device__ inline double ld(const float *p, int64_t q) {
   return (double)*(const float *)((const char *)p + (Off)(q * 4));
 }
 
+// fields read or written once per cell (the snapshots before and after, the
+// output): non-temporal, so that they do not push the neighbour rows and
+// planes of u out of L2 before the next waves reuse them
+template <typename Off>
+__device__ inline double ld_once(const float *p, int64_t q) {
+  return (double)__builtin_nontemporal_load((const float *)((const char *)p + (Off)(q * 4)));
+}
+
 // position of R_ij in the stress list: 2-D (uu, vv, uv), 3-D (uu, vv, ww, uv, uw, vw)
 __device__ constexpr int sidx(int i, int j, int nd) {
   return i == j ? i : nd == 2 ? 2 : ((i < j ? i : j) == 0 ? ((i < j ? j : i) == 1 ? 3 : 4) : 5);
@@ -168,7 +176,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_flow(Args a) {
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
       if (MODEL == PI_FLOW_NS) {
-        if (!a.steady) acc[i] += (ld<Off>(a.un[i], c) - ld<Off>(a.up[i], c)) * a.inv2dt;
+        if (!a.steady) acc[i] += (ld_once<Off>(a.un[i], c) - ld_once<Off>(a.up[i], c)) * a.inv2dt;
         out[i] = -a.rho * acc[i] + a.mu * lap[i];
       } else {
         out[i] = -a.rho * acc[i];
@@ -250,7 +258,7 @@ __global__ __launch_bounds__(kWave *kWavesPerBlock) void k_flow(Args a) {
     }
   }
 #pragma unroll
-  for (int i = 0; i < ND; ++i) *(float *)((char *)a.f[i] + (Off)(c * 4)) = (float)out[i];
+  for (int i = 0; i < ND; ++i) __builtin_nontemporal_store((float)out[i], (float *)((char *)a.f[i] + (Off)(c * 4)));
 }
 
 }  // namespace pf
