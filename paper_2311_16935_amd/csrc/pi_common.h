@@ -126,6 +126,8 @@ struct Inst {
   int32_t bicg;     // inner solver is BiCGStab (else the single-pass CG)
   int32_t cg_inline;// the CG passes take alpha and beta from the previous
                     // pass's partials themselves (no finalize kernel)
+  int32_t nt_outer; // the outer kernel streams S, P' and r non-temporally
+                    // (chosen by the autotuner)
   int32_t ncomp;    // connected groups of data cells
   int32_t inner_iters; // inner Krylov iterations per outer step
   int32_t inner_op; // operator of the inner solve: 0 [W^{n+1}], 1 [W^{n+1}] - [W^n]

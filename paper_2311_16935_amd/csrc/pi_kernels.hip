@@ -92,6 +92,41 @@ __device__ inline void stv(PI_G T *p, int64_t c, const Vec<T, W> &v) {
   }
 }
 
+// Streams that one kernel writes (or reads at the cell only) and that the
+// next kernel of the step reads again from memory: non-temporal, so they do
+// not displace the neighbour rows that other waves are about to re-read
+// from L2 (the CG passes always; the outer kernel where the autotuner
+// measured it faster).
+template <int W, typename T>
+__device__ inline void stv_nt(PI_G T *p, int64_t c, const Vec<T, W> &v) {
+  if constexpr (W * sizeof(T) >= 16) {
+    PI_G u32x4 *q = (PI_G u32x4 *)(p + c);
+#pragma unroll
+    for (int i = 0; i < (int)(W * sizeof(T) / 16); ++i) {
+      u32x4 u;
+      memcpy(&u, &v.e[i * (16 / sizeof(T))], 16);
+      __builtin_nontemporal_store(u, q + i);
+    }
+  } else {
+    stv<W>(p, c, v);
+  }
+}
+template <int W, typename T>
+__device__ inline Vec<T, W> ldv_nt(const PI_G T *p, int64_t c) {
+  if constexpr (W * sizeof(T) >= 16) {
+    Vec<T, W> v;
+    const PI_G u32x4 *q = (const PI_G u32x4 *)(p + c);
+#pragma unroll
+    for (int i = 0; i < (int)(W * sizeof(T) / 16); ++i) {
+      const u32x4 u = __builtin_nontemporal_load(q + i);
+      memcpy(&v.e[i * (16 / sizeof(T))], &u, 16);
+    }
+    return v;
+  } else {
+    return ldv<W>(p, c);
+  }
+}
+
 template <typename V, int W>
 __device__ inline Vec<V, W> vzero() {
   Vec<V, W> z;
@@ -721,6 +756,7 @@ __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Ins
   const bool use_d = pd.use_d;
   const PI_G double *S = gp<double>(in.S64);
   PI_G T *res = gp<T>(in.res);
+  const bool nt = in.nt_outer != 0;  // uniform over the launch
   const int bits = dir_bits(ND);
   double a[6];
 #pragma unroll
@@ -750,7 +786,7 @@ __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Ins
   };
   auto load1 = [&](int64_t c) -> double { return Pold[c] + (double)((use_d ? dl[c] : T(0)) + at * pt[c]); };
   auto aux = [&](int64_t c) {
-    const Vec<double, W> s = ldv<W>(S, c);
+    const Vec<double, W> s = nt ? ldv_nt<W>(S, c) : ldv<W>(S, c);
     const Vec<T, W> d = delta(c);
     Vec<Aux, W> x;
 #pragma unroll
@@ -794,8 +830,13 @@ __global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Ins
       p.e[k] = o[k].p;
       r.e[k] = (T)o[k].r;
     }
-    stv<W>(Pnew, c, p);
-    stv<W>(res, c, r);
+    if (nt) {
+      stv_nt<W>(Pnew, c, p);
+      stv_nt<W>(res, c, r);
+    } else {
+      stv<W>(Pnew, c, p);
+      stv<W>(res, c, r);
+    }
   };
   march<ND, W, GEN, double, Aux, Out>(wk, load, load1, aux, body, store);
   publish<4>(in, part, e.lb, acc);
@@ -967,7 +1008,7 @@ __device__ __forceinline__ void cg_step_body(const BlockEnt *tab, const Inst *in
   auto load1 = [&](int64_t c) -> T { return (cg.rold[c] - cg.al * cg.qold[c]) + cg.be * cg.pold[c]; };
   auto aux = [&](int64_t c) {
     const Vec<T, W> r = ldv<W>(cg.rold, c), q = ldv<W>(cg.qold, c), p = ldv<W>(cg.pold, c);
-    const Vec<T, W> d = cg.rd_d ? ldv<W>(cg.d, c) : vzero<T, W>();
+    const Vec<T, W> d = cg.rd_d ? ldv_nt<W>(cg.d, c) : vzero<T, W>();
     Vec<Aux, W> x;
 #pragma unroll
     for (int k = 0; k < W; ++k) x.e[k] = Aux{r.e[k] - cg.al * q.e[k], d.e[k] + cg.al * p.e[k]};
@@ -995,10 +1036,10 @@ __device__ __forceinline__ void cg_step_body(const BlockEnt *tab, const Inst *in
       rv.e[k] = o[k].r;
       dv.e[k] = o[k].d;
     }
-    stv<W>(cg.pnew, c, pv);
-    stv<W>(cg.qnew, c, qv);
-    stv<W>(cg.rnew, c, rv);
-    if (cg.wr_d) stv<W>(cg.d, c, dv);
+    stv_nt<W>(cg.pnew, c, pv);
+    stv_nt<W>(cg.qnew, c, qv);
+    stv_nt<W>(cg.rnew, c, rv);
+    if (cg.wr_d) stv_nt<W>(cg.d, c, dv);
   };
   if constexpr (FIRST) {
     // p_0 = r_0: only the residual is read; p and q are written
@@ -1018,8 +1059,8 @@ __device__ __forceinline__ void cg_step_body(const BlockEnt *tab, const Inst *in
         pv.e[k] = o[k].p;
         qv.e[k] = o[k].q;
       }
-      stv<W>(cg.pnew, c, pv);
-      stv<W>(cg.qnew, c, qv);
+      stv_nt<W>(cg.pnew, c, pv);
+      stv_nt<W>(cg.qnew, c, qv);
     };
     march<ND, W, GEN, T, Aux, Out>(wk, load0, load01, aux0, body, store0);
   } else {
@@ -1809,10 +1850,10 @@ __device__ __forceinline__ void cg_step_cc_body(const BlockEnt *tab, const Inst 
       rv.e[k] = o[k].r;
       dv.e[k] = o[k].d;
     }
-    stv<W>(cg.pnew, c, pv);
-    stv<W>(cg.qnew, c, qv);
-    stv<W>(cg.rnew, c, rv);
-    if (cg.wr_d) stv<W>(cg.d, c, dv);
+    stv_nt<W>(cg.pnew, c, pv);
+    stv_nt<W>(cg.qnew, c, qv);
+    stv_nt<W>(cg.rnew, c, rv);
+    if (cg.wr_d) stv_nt<W>(cg.d, c, dv);
   };
   if constexpr (FIRST) {
     // p_0 = r_0: only the residual is read; p and q are written

@@ -761,15 +761,15 @@ out:
   return rc;
 }
 
-// tile cache of pi_autotune: (ndim, nx, ny, nz, fp64, bicgstab) -> (mseg, lane cells)
+// tile cache of pi_autotune: (ndim, nx, ny, nz, fp64, bicgstab) -> (mseg, lane cells, non-temporal outer)
 static std::mutex g_tune_mu;
-static std::map<std::array<int64_t, 6>, std::array<int32_t, 2>> g_tune;
+static std::map<std::array<int64_t, 6>, std::array<int32_t, 3>> g_tune;
 
 extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, void *stream) {
   if (!p || reps < 1) return PI_ERR_INVALID_ARG;
   const std::array<int64_t, 6> key = {p->ndim, p->dims[0], p->dims[1], p->dims[2], p->fp64,
                                       (p->bicgstab ? 1 : 0) | (p->cc ? 2 : 0)};
-  std::array<int32_t, 2> best = {-1, 0};
+  std::array<int32_t, 3> best = {-1, 0, 0};
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune.find(key);
@@ -778,6 +778,7 @@ extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, v
   pi_status rc;
   if (best[0] < 0) {
     std::vector<std::array<int32_t, 2>> cand;
+    p->inst.nt_outer = 0;
     std::vector<int32_t> widths;
     if (p->dims[0] % 4 == 0) widths.push_back(4);
     if (p->dims[0] % 2 == 0 && !p->cc) widths.push_back(2);
@@ -798,12 +799,21 @@ extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, v
       const double step = t_outer + p->inner_iters * t_inner;
       if (step < best_ms) {
         best_ms = step;
-        best = {p->inst.mseg, p->inst.vw};
+        best = {p->inst.mseg, p->inst.vw, 0};
       }
     }
+    // at the chosen tile: the outer kernel's streams plain or non-temporal
+    if ((rc = pi_set_tile(p, best[0], best[1])) != PI_OK) return rc;
+    double t_nt[2] = {0.0, 0.0};
+    for (int nt = 0; nt < 2; ++nt) {
+      p->inst.nt_outer = nt;
+      if ((rc = pi_time_kernel(p, PI_K_OUTER, reps, &t_nt[nt], stream)) != PI_OK) return rc;
+    }
+    best[2] = t_nt[1] < t_nt[0] ? 1 : 0;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[key] = best;
   }
+  p->inst.nt_outer = best[2];
   rc = pi_set_tile(p, best[0], best[1]);
   if (rc == PI_OK && mseg_out) *mseg_out = p->inst.mseg;
   return rc;
