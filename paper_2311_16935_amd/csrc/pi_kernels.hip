@@ -605,7 +605,7 @@ __device__ inline bool skip_inner(const Inst &in, const State *st) {
 // set-up: P^0 and the source vector
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_init(const BlockEnt *tab, const Inst *insts, State *sts, double *part,
+__global__ __launch_bounds__(kBlock) void k_init(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts, double *part,
                                                  int warm) {
   PI_PROLOGUE
   int64_t beg, end;
@@ -648,7 +648,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const BlockEnt *tab, const Inst
 // group; a float copy would not, and its constant part would put a floor of
 // about 6e-8 / sqrt(cells) under the reachable residual.
 template <typename T, int ND>
-__global__ __launch_bounds__(kBlock) void k_source(const BlockEnt *tab, const Inst *insts, State *sts, double *part) {
+__global__ __launch_bounds__(kBlock) void k_source(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts, double *part) {
   PI_PROLOGUE
   int64_t beg, end;
   linear_range(in, e.lb, beg, end);
@@ -742,7 +742,7 @@ __device__ inline Pending<T> pending(const Inst &in, const State *st, const doub
 // delta = d + alpha p (the residual it would also update is recomputed from
 // scratch anyway), which saves one pass over four vectors per outer step.
 template <typename T, int ND, int W, bool GEN>
-__global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Inst *insts, State *sts, double *part) {
+__global__ __launch_bounds__(kBlock) void k_outer(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts, double *part) {
   PI_PROLOGUE
   if (skip_outer(st)) return;
   const Walk wk = make_walk<W>(in, e.lb);
@@ -975,7 +975,7 @@ __device__ inline double *cg_part(const Inst &in, double *part, int k) {
 }
 
 template <typename T, int ND, int W, bool GEN, bool FIRST>
-__device__ __forceinline__ void cg_step_body(const BlockEnt *tab, const Inst *insts, State *sts, double *part,
+__device__ __forceinline__ void cg_step_body(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts, double *part,
                                              int kpass) {
   PI_PROLOGUE
   const CgPass<T> cg = cg_pass<T>(in, st, part, e.lb, kpass);
@@ -1072,12 +1072,12 @@ __device__ __forceinline__ void cg_step_body(const BlockEnt *tab, const Inst *in
 // pass 0 of an outer step and the passes after it, compiled apart so that
 // each gets its own register allocation
 template <typename T, int ND, int W, bool GEN>
-__global__ __launch_bounds__(kBlock) void k_cg_first(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_cg_first(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts,
                                                      double *part, int kpass) {
   cg_step_body<T, ND, W, GEN, true>(tab, insts, sts, part, kpass);
 }
 template <typename T, int ND, int W, bool GEN>
-__global__ __launch_bounds__(kBlock) void k_cg_step(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_cg_step(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts,
                                                     double *part, int kpass) {
   cg_step_body<T, ND, W, GEN, false>(tab, insts, sts, part, kpass);
 }
@@ -1087,7 +1087,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_step(const BlockEnt *tab, const I
 // ---------------------------------------------------------------------------
 // phase 1: p <- r + beta (p - omega v) (p <- r first), v' <- M p (into q), rhat.v'
 template <typename T, int ND, int W, bool GEN>
-__global__ __launch_bounds__(kBlock) void k_bicg_spmv_p(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_bicg_spmv_p(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts,
                                                         double *part) {
   PI_PROLOGUE
   if (skip_inner(in, st)) return;
@@ -1143,7 +1143,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg_spmv_p(const BlockEnt *tab, con
 
 // phase 2: v <- v', s <- r - alpha v, t <- M s, t.s and t.t
 template <typename T, int ND, int W, bool GEN>
-__global__ __launch_bounds__(kBlock) void k_bicg_spmv_s(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_bicg_spmv_s(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts,
                                                         double *part) {
   PI_PROLOGUE
   if (skip_inner(in, st)) return;
@@ -1237,7 +1237,7 @@ struct BicgUpdate {
 };
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_bicg_update(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_bicg_update(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts,
                                                         double *part) {
   PI_PROLOGUE
   if (skip_inner(in, st)) return;
@@ -1261,7 +1261,7 @@ __global__ __launch_bounds__(kBlock) void k_bicg_update(const BlockEnt *tab, con
 
 // copy of the outer residual used as BiCGStab's shadow vector
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_copy_res(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_copy_res(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts,
                                                      double *part) {
   PI_PROLOGUE
   if (skip_outer(st)) return;
@@ -1278,7 +1278,7 @@ __global__ __launch_bounds__(kBlock) void k_copy_res(const BlockEnt *tab, const 
 // Single group: fixed-order block partials.  Several groups: one block per
 // segment of the group-sorted cell list (fixed order inside), then one thread
 // per group sums its segments in order -- deterministic in both cases.
-__global__ __launch_bounds__(kBlock) void k_gauge_sum(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_gauge_sum(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts,
                                                       double *part) {
   PI_PROLOGUE
   const double *P = in.P[st->Pcur];
@@ -1301,7 +1301,7 @@ __global__ __launch_bounds__(kBlock) void k_gauge_sum(const BlockEnt *tab, const
   publish<1>(in, part, e.lb, acc);
 }
 
-__global__ __launch_bounds__(kBlock) void k_gauge_groups(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_gauge_groups(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts,
                                                          double *part) {
   PI_PROLOGUE
   if (in.ncomp <= 1) return;
@@ -1313,7 +1313,7 @@ __global__ __launch_bounds__(kBlock) void k_gauge_groups(const BlockEnt *tab, co
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gauge_apply(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_gauge_apply(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts,
                                                         double *part) {
   PI_PROLOGUE
   int64_t beg, end;
@@ -1344,7 +1344,7 @@ __global__ __launch_bounds__(kBlock) void k_gauge_apply(const BlockEnt *tab, con
 // finalize: one block per instance sums the partials of the kernel that just
 // ran (fixed order) and updates the instance's scalars
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *sts, const double *part, int kind,
+__global__ __launch_bounds__(kBlock) void k_finalize(const Inst *__restrict__ insts, State *__restrict__ sts, const double *part, int kind,
                                                     int kpass) {
   const Inst &in = insts[blockIdx.x];
   State *st = sts + blockIdx.x;
@@ -1457,7 +1457,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *insts, State *s
 // plain operator applies (pi_apply): y = M x, N x or (M - N) x
 // ---------------------------------------------------------------------------
 template <typename T, int ND, int W, bool GEN>
-__global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Inst *insts, State *sts, double *part,
+__global__ __launch_bounds__(kBlock) void k_apply(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts, double *part,
                                                   int op, const T *x_, T *y_) {
   PI_PROLOGUE
   const PI_G T *x = gp<T>(x_);
@@ -1557,7 +1557,7 @@ __device__ inline bool cc_has(uint32_t cd, int j) { return (cd >> cc_bit(cc_dx(j
 // neighbours J with data (the sum of the two weights is the direction's
 // total a_J), FP64
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_source_cc(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_source_cc(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts,
                                                      double *part) {
   PI_PROLOGUE
   int64_t beg, end;
@@ -1700,7 +1700,7 @@ __device__ inline void march_cc(const Walk &wk, Load load, Load1 load1, Aux aux,
 // P' = P + delta (the pending last CG step folded in as in k_outer),
 // r = S - (M - N) P' with (M - N) P' = sum_J a_J (P'_C - P'_J)
 template <typename T, int W>
-__global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts,
                                                     double *part) {
   PI_PROLOGUE
   if (skip_outer(st)) return;
@@ -1781,7 +1781,7 @@ __global__ __launch_bounds__(kBlock) void k_outer_cc(const BlockEnt *tab, const 
 // One inner CG iteration with the previous one's update folded in, as
 // k_cg_step, for the cell-centred scheme.
 template <typename T, int W, bool FIRST>
-__device__ __forceinline__ void cg_step_cc_body(const BlockEnt *tab, const Inst *insts, State *sts, double *part,
+__device__ __forceinline__ void cg_step_cc_body(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts, double *part,
                                                 int kpass) {
   PI_PROLOGUE
   const CgPass<T> cg = cg_pass<T>(in, st, part, e.lb, kpass);
@@ -1884,19 +1884,19 @@ __device__ __forceinline__ void cg_step_cc_body(const BlockEnt *tab, const Inst 
 }
 
 template <typename T, int W>
-__global__ __launch_bounds__(kBlock) void k_cg_first_cc(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_cg_first_cc(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts,
                                                        double *part, int kpass) {
   cg_step_cc_body<T, W, true>(tab, insts, sts, part, kpass);
 }
 template <typename T, int W>
-__global__ __launch_bounds__(kBlock) void k_cg_step_cc(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_cg_step_cc(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts,
                                                       double *part, int kpass) {
   cg_step_cc_body<T, W, false>(tab, insts, sts, part, kpass);
 }
 
 // y = M x, N x or (M - N) x for pi_apply
 template <typename T, int W>  // W: the plan's lane width; this kernel takes contiguous ranges
-__global__ __launch_bounds__(kBlock) void k_apply_cc(const BlockEnt *tab, const Inst *insts, State *sts,
+__global__ __launch_bounds__(kBlock) void k_apply_cc(const BlockEnt *tab, const Inst *__restrict__ insts, State *__restrict__ sts,
                                                     double *part, int op, const T *x, T *y) {
   PI_PROLOGUE
   int64_t beg, end;
