@@ -301,7 +301,9 @@ pi_status pi_time_kernel(pi_plan_t plan, int kernel, int32_t reps, double *avg_m
  * outer step of Algorithm 1 for this plan: for each candidate (segment
  * length, cells per lane) it times the outer kernel once and the inner CG
  * pass `inner_iters` times
- * (pi_time_kernel, `reps` launches each) and keeps the fastest.  Results are
+ * (pi_time_kernel, `reps` launches each), times the three fastest again with
+ * 4 * reps launches and keeps the fastest of those; then it chooses between
+ * plain and non-temporal streams in the outer kernel (4 * reps launches each).  Results are
  * cached per (ndim, dims, precision, inner solver) for the life of the process,
  * so later plans of the same shape take the cached tile without timing.  The
  * chosen segment length is returned in *mseg (may be NULL).  Overwrites the

@@ -702,14 +702,14 @@ extern "C" pi_status pi_apply(pi_plan_t p, int op, const void *x, void *y, void 
   return PI_OK;
 }
 
-extern "C" pi_status pi_time_kernel(pi_plan_t p, int kernel, int32_t reps, double *avg_ms, void *stream_) {
-  if (!p || !avg_ms || reps < 1 || (kernel != PI_K_OUTER && kernel != PI_K_INNER)) return PI_ERR_INVALID_ARG;
-  if (kernel == PI_K_INNER && p->bicgstab) return PI_ERR_INVALID_ARG;
-  if (!has_table(p)) return PI_ERR_OOM;
-  hipStream_t stream = (hipStream_t)stream_;
-  const Launcher L = single_launcher(p);
-  // a mid-solve state: a correction is pending, the search direction is not
-  // the first one, no convergence, never reaching the tolerance
+namespace {
+
+// A mid-solve state for timing single launches: a correction is pending, the
+// search direction is not the first one, no convergence, never reaching the
+// tolerance.  CG pass 2 (reads and writes the correction) and the outer
+// kernel read pass 1's partial sums: alpha = 1e-3 and beta = 1, finite and
+// fixed.
+pi_status timing_state(pi_plan_t p, hipStream_t stream) {
   Inst in = p->inst;
   in.tol = -1.0;
   in.max_iter = INT64_MAX;
@@ -722,9 +722,6 @@ extern "C" pi_status pi_time_kernel(pi_plan_t p, int kernel, int32_t reps, doubl
   st.alpha = 1e-3;
   st.beta = 0.5;
   st.normS2 = 1.0;
-  const KernelId k = kernel == PI_K_OUTER ? K_OUTER : K_CG_STEP;
-  // CG pass 2 (reads and writes the correction) and the outer kernel read
-  // pass 1's partial sums: alpha = 1e-3 and beta = 1, finite and fixed
   std::vector<double> slots((size_t)p->inst.nblocks * 4);
   for (int i = 0; i < p->inst.nblocks; ++i) {
     slots[4 * i + 0] = 1e3;  // p.q
@@ -732,23 +729,26 @@ extern "C" pi_status pi_time_kernel(pi_plan_t p, int kernel, int32_t reps, doubl
     slots[4 * i + 2] = 0.0;  // q.q
     slots[4 * i + 3] = 1.0;  // r.r
   }
-  const int kpass = 2;
-  hipEvent_t a = nullptr, b = nullptr;
-  pi_status rc = PI_ERR_DEVICE;
-  float ms = 0.f;
   if (hipMemcpyAsync(p->d_inst, &in, sizeof(Inst), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemcpyAsync(p->d_state, &st, sizeof(State), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemcpyAsync(p->d_part + (size_t)(1 + 1) * in.part_stride * 4 + (size_t)in.part_base * 4, slots.data(),
                      slots.size() * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess)
     return PI_ERR_DEVICE;
+  return PI_OK;
+}
+
+// Average time of `reps` back-to-back launches of f (after one warm-up).
+template <class F>
+pi_status time_launches(hipStream_t stream, int32_t reps, double *avg_ms, F &&f) {
+  hipEvent_t a = nullptr, b = nullptr;
+  pi_status rc = PI_ERR_DEVICE;
+  float ms = 0.f;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) goto out;
-  // the kernel alone: without its finalize the state, and so every launch,
-  // stays the same
-  if (L.go(k, stream, kpass, nullptr, nullptr, false) != hipSuccess) goto out;  // warm-up launch
+  if (f() != hipSuccess) goto out;  // warm-up launch
   if (hipEventRecord(a, stream) != hipSuccess) goto out;
   for (int i = 0; i < reps; ++i)
-    if (L.go(k, stream, kpass, nullptr, nullptr, false) != hipSuccess) goto out;
+    if (f() != hipSuccess) goto out;
   if (hipEventRecord(b, stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
       hipEventElapsedTime(&ms, a, b) != hipSuccess)
     goto out;
@@ -759,6 +759,37 @@ out:
   if (b) (void)hipEventDestroy(b);
   (void)hipStreamSynchronize(stream);
   return rc;
+}
+
+// Per-pass cost of the CG finalize kernel for the plan's current table
+// (zero when its CG passes sum the partials themselves): back-to-back
+// launches, so the gap between kernels is included as in a solve.
+pi_status time_cg_finalize(pi_plan_t p, int32_t reps, double *avg_ms, hipStream_t stream) {
+  *avg_ms = 0.0;
+  if (p->bicgstab || p->inst.cg_inline) return PI_OK;
+  pi_status rc = timing_state(p, stream);
+  if (rc != PI_OK) return rc;
+  const int kpass = 2;
+  return time_launches(stream, reps, avg_ms, [&] {
+    return launch_finalize(K_CG_STEP, p->d_inst, p->d_state, p->d_part, 1, stream, kpass);
+  });
+}
+
+}  // namespace
+
+extern "C" pi_status pi_time_kernel(pi_plan_t p, int kernel, int32_t reps, double *avg_ms, void *stream_) {
+  if (!p || !avg_ms || reps < 1 || (kernel != PI_K_OUTER && kernel != PI_K_INNER)) return PI_ERR_INVALID_ARG;
+  if (kernel == PI_K_INNER && p->bicgstab) return PI_ERR_INVALID_ARG;
+  if (!has_table(p)) return PI_ERR_OOM;
+  hipStream_t stream = (hipStream_t)stream_;
+  const Launcher L = single_launcher(p);
+  const KernelId k = kernel == PI_K_OUTER ? K_OUTER : K_CG_STEP;
+  pi_status rc = timing_state(p, stream);
+  if (rc != PI_OK) return rc;
+  // the kernel alone: without its finalize the state, and so every launch,
+  // stays the same
+  const int kpass = 2;
+  return time_launches(stream, reps, avg_ms, [&] { return L.go(k, stream, kpass, nullptr, nullptr, false); });
 }
 
 // tile cache of pi_autotune: (ndim, nx, ny, nz, fp64, bicgstab) -> (mseg, lane cells, non-temporal outer)
@@ -789,17 +820,36 @@ extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, v
       for (int32_t m = 2; m <= 256; m *= 2)
         if (m < p->inst.nm && m != p->inst.mseg) cand.push_back({m, vw});
     }
+    // time of one outer step at a candidate tile
+    auto step_ms = [&](const std::array<int32_t, 2> &c, int32_t r, double *ms) -> pi_status {
+      pi_status e;
+      if ((e = pi_set_tile(p, c[0], c[1])) != PI_OK) return e;
+      double t_outer = 0.0, t_inner = 0.0, t_fin = 0.0;
+      if ((e = pi_time_kernel(p, PI_K_OUTER, r, &t_outer, stream)) != PI_OK ||
+          (!p->bicgstab && (e = pi_time_kernel(p, PI_K_INNER, r, &t_inner, stream)) != PI_OK) ||
+          (e = time_cg_finalize(p, r, &t_fin, (hipStream_t)stream)) != PI_OK)
+        return e;
+      *ms = t_outer + p->inner_iters * (t_inner + t_fin);
+      return PI_OK;
+    };
+    // every candidate once, then the three fastest again with four times the
+    // launches: single short timings differ by a few percent from run to run,
+    // about as much as neighbouring tiles do
+    std::vector<std::pair<double, size_t>> first;
+    for (size_t i = 0; i < cand.size(); ++i) {
+      double ms = 0.0;
+      if ((rc = step_ms(cand[i], reps, &ms)) != PI_OK) return rc;
+      first.push_back({ms, i});
+    }
+    std::sort(first.begin(), first.end());
     double best_ms = 1e300;
-    for (const auto &c : cand) {
-      if ((rc = pi_set_tile(p, c[0], c[1])) != PI_OK) return rc;
-      double t_outer = 0.0, t_inner = 0.0;
-      if ((rc = pi_time_kernel(p, PI_K_OUTER, reps, &t_outer, stream)) != PI_OK ||
-          (!p->bicgstab && (rc = pi_time_kernel(p, PI_K_INNER, reps, &t_inner, stream)) != PI_OK))
-        return rc;
-      const double step = t_outer + p->inner_iters * t_inner;
-      if (step < best_ms) {
-        best_ms = step;
-        best = {p->inst.mseg, p->inst.vw, 0};
+    for (size_t j = 0; j < first.size() && j < 3; ++j) {
+      const auto &c = cand[first[j].second];
+      double ms = 0.0;
+      if ((rc = step_ms(c, 4 * reps, &ms)) != PI_OK) return rc;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = {c[0], c[1], 0};
       }
     }
     // at the chosen tile: the outer kernel's streams plain or non-temporal
@@ -807,7 +857,7 @@ extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, v
     double t_nt[2] = {0.0, 0.0};
     for (int nt = 0; nt < 2; ++nt) {
       p->inst.nt_outer = nt;
-      if ((rc = pi_time_kernel(p, PI_K_OUTER, reps, &t_nt[nt], stream)) != PI_OK) return rc;
+      if ((rc = pi_time_kernel(p, PI_K_OUTER, 4 * reps, &t_nt[nt], stream)) != PI_OK) return rc;
     }
     best[2] = t_nt[1] < t_nt[0] ? 1 : 0;
     std::lock_guard<std::mutex> g(g_tune_mu);
