@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--kernel-reps", type=int, default=20)
-    ap.add_argument("--mode", choices=("solve", "kernels", "batched", "flow", "sequence"), default="solve",
+    ap.add_argument("--mode", choices=("solve", "kernels", "batched", "flow", "sequence", "unet"), default="solve",
                     help="kernels: only time the outer-step kernels and a copy of known size (for counters); "
                          "batched: the uneven batch of 2-D snapshots and 3-D volumes in one batched solve")
     ap.add_argument("--count2d", type=int, default=512, help="batched mode: 2-D instances")
@@ -352,6 +352,7 @@ def kernel_mode(args, pi, plan, grads, P, ncell, bytes_per_cell=BYTES_PER_CELL):
     torch.cuda.synchronize()
     res["bitwise_not"] = {"bytes_read": 4 * ncell, "bytes_written": 4 * ncell, "launches": args.kernel_reps}
     print(json.dumps({"mode": "kernels", "n": args.n, "cells": ncell, "tile": pi.pi_get_tile(plan.handle),
+                      "lane_cells": pi.pi_get_lane_cells(plan.handle),
                       "workload": args.workload, "cell_centered": bool(args.cell_centered),
                       "kernels": res, "kernel_source_sha256": kernel_source_hash()}), flush=True)
 
@@ -712,6 +713,71 @@ def sequence_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def unet_mode(args):
+    """The warm-start network's BF16 matrix-core layers at the training
+    shapes 128^3 (batch 4) and 256^3 (batch 1): forward and training-step
+    time (HIP events on the current stream) and TFLOP/s against the dense
+    BF16 peak, per layer for the 3x3x3 convolutions of each level.  Random
+    weights and inputs: the work does not depend on the values."""
+    import math
+
+    import torch
+
+    from paper_2311_16935_amd import unet as U
+    from paper_2311_16935_amd.warmstart import UNet
+
+    dev = "cuda:0"
+    peak = 2500.0
+    out = {}
+    for res, batch in ((128, 4), (256, 1)):
+        net = UNet(device=dev, seed=0)
+        B = net.buffers(batch, (res, res, res))
+        B["x0"].copy_(torch.randn(B["x0"].shape, device=dev).to(torch.bfloat16))
+        tgt = torch.randn((batch, res, res, res), device=dev)
+        flops = 0
+        for L in net.layers.values():
+            if L.kind in ("conv", "up"):
+                lvl = int(L.name[3]) if L.kind == "conv" else int(L.name[2]) + 1
+                flops += 2 * batch * (res >> lvl) ** 3 * L.cout * L.taps * L.cin
+
+        def timed(fn, n=5):
+            for _ in range(2):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(n):
+                fn()
+            e1.record()
+            e1.synchronize()
+            return e0.elapsed_time(e1) / n
+
+        fw = timed(lambda: net.forward(B))
+        tr = timed(lambda: net.train_step(B, tgt, 1e-5))
+        T, R = U.tensor, B["R"]
+        layers = {}
+        for name in ("enc0b", "enc1b", "enc2b", "enc3b", "dec0a"):
+            L = net.layers[name]
+            lvl = int(name[3])
+            src = T(B["cat0"]) if name == "dec0a" else T(B[f"t{lvl}"])
+            dst = T(B["ua0"]) if name == "dec0a" else (T(B["bot"]) if lvl == 3 else T(B[f"t{lvl}"], 0, L.cout))
+            if name in ("enc0b", "enc1b", "enc2b"):
+                dst = T(B[f"ua{lvl}"])
+            ms = timed(lambda: net._conv(name, src, dst, R[lvl]))
+            f = 2 * batch * (res >> lvl) ** 3 * L.cout * 27 * L.cin
+            layers[name] = {"ms": ms, "TFLOPs": f / ms / 1e9, "M": batch * (res >> lvl) ** 3, "N": L.cout,
+                            "K": 27 * L.cin}
+        key = f"{res}^3_batch{batch}"
+        out[key] = {"forward_ms": fw, "forward_TFLOPs": flops / fw / 1e9,
+                    "forward_frac_of_peak": flops / fw / 1e9 / peak, "train_step_ms": tr,
+                    "train_step_TFLOPs": 3 * flops / tr / 1e9, "layers": layers}
+        progress(f"{key}: forward {fw:.2f} ms ({flops / fw / 1e9:.0f} TFLOP/s), train step {tr:.1f} ms")
+        net.release()
+        del net, B, tgt
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "unet", "peak_TFLOPs": peak, "dtype": "bf16 (fp32 accumulate)", "results": out}),
+          flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -726,6 +792,9 @@ def main():
         return
     if args.mode == "sequence":
         sequence_mode(args)
+        return
+    if args.mode == "unet":
+        unet_mode(args)
         return
     import torch
 
@@ -764,7 +833,7 @@ def main():
     if not args.no_autotune:
         t0 = time.perf_counter()
         m = plan.autotune(reps=5)
-        tune = {"mseg": m, "seconds": time.perf_counter() - t0}
+        tune = {"mseg": m, "lane_cells": pi.pi_get_lane_cells(plan.handle), "seconds": time.perf_counter() - t0}
         progress(f"autotuned tile: {m} planes per segment ({tune['seconds']:.1f} s, outside the timed region)")
     if args.mode == "kernels":
         kernel_mode(args, pi, plan, grads, P, ncell, bytes_per_cell)
