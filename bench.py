@@ -45,6 +45,9 @@ BYTES_PER_CELL = {
     "k_outer": 8 + 4 + 4 + 8 + 8 + 4,   # P, d, p (last CG step folded in), S (FP64) in; P', r out
     "k_cg_step": 4 * 4 + 4 * 4,         # r, q, p, delta in; r', q', p', delta out
 }
+# a plan whose CG passes evaluate q = M p again (pi_get_cg_recompute) moves
+# r, p, delta in and r', p', delta out
+CG_RECOMPUTE_BYTES = 3 * 4 + 3 * 4
 # the cell-centred kernels always read the 4-byte ring code of each cell
 BYTES_PER_CELL_CC = {k: v + 4 for k, v in BYTES_PER_CELL.items()}
 TIMED = (("k_outer", 0), ("k_cg_step", 1))  # names and pi_time_kernel ids (PI_K_OUTER, PI_K_INNER)
@@ -342,7 +345,7 @@ def kernel_mode(args, pi, plan, grads, P, ncell, bytes_per_cell=BYTES_PER_CELL):
         res[name] = {"avg_ms": ms, "launches": args.kernel_reps + 1,
                      "alg_bytes": bytes_per_cell[name] * ncell,
                      "achieved_GBs": bytes_per_cell[name] * ncell / (ms * 1e-3) / 1e9}
-    res["k_apply"] = time_apply(pi, plan, args.kernel_reps, bytes_per_cell["k_cg_step"] - 32)
+    res["k_apply"] = time_apply(pi, plan, args.kernel_reps, bytes_per_cell.get("code", 0))
     # yardstick with a kernel name nothing else here uses: reads and writes
     # 4 bytes per element
     x = torch.randint(0, 1 << 30, (ncell,), dtype=torch.int32, device="cuda:0")
@@ -353,6 +356,7 @@ def kernel_mode(args, pi, plan, grads, P, ncell, bytes_per_cell=BYTES_PER_CELL):
     res["bitwise_not"] = {"bytes_read": 4 * ncell, "bytes_written": 4 * ncell, "launches": args.kernel_reps}
     print(json.dumps({"mode": "kernels", "n": args.n, "cells": ncell, "tile": pi.pi_get_tile(plan.handle),
                       "lane_cells": pi.pi_get_lane_cells(plan.handle),
+                      "cg_recompute": pi.pi_get_cg_recompute(plan.handle),
                       "workload": args.workload, "cell_centered": bool(args.cell_centered),
                       "kernels": res, "kernel_source_sha256": kernel_source_hash()}), flush=True)
 
@@ -824,17 +828,22 @@ def main():
         ncell *= v
     # a masked grid reads the 4-byte counter code in both stencil kernels
     bytes_per_cell = dict(BYTES_PER_CELL_CC if cc else BYTES_PER_CELL)
+    bytes_per_cell["code"] = 4 if cc else 0
     if mask is not None and not cc:
         bytes_per_cell["k_outer"] += 4
         bytes_per_cell["k_cg_step"] += 4
+        bytes_per_cell["code"] = 4
     progress(f"plan ready: {workload}, tile {pi.pi_get_tile(plan.handle)}, "
              f"{plan.workspace_bytes / 2**30:.2f} GiB, {pi.lib.pi_get_lane_cells(plan.handle)} cells per lane")
     tune = None
     if not args.no_autotune:
         t0 = time.perf_counter()
         m = plan.autotune(reps=5)
-        tune = {"mseg": m, "lane_cells": pi.pi_get_lane_cells(plan.handle), "seconds": time.perf_counter() - t0}
+        tune = {"mseg": m, "lane_cells": pi.pi_get_lane_cells(plan.handle),
+                "cg_recompute": pi.pi_get_cg_recompute(plan.handle), "seconds": time.perf_counter() - t0}
         progress(f"autotuned tile: {m} planes per segment ({tune['seconds']:.1f} s, outside the timed region)")
+    if pi.pi_get_cg_recompute(plan.handle):
+        bytes_per_cell["k_cg_step"] = CG_RECOMPUTE_BYTES + bytes_per_cell["code"]
     if args.mode == "kernels":
         kernel_mode(args, pi, plan, grads, P, ncell, bytes_per_cell)
         return
@@ -875,7 +884,7 @@ def main():
     for name in kern:
         kern[name]["launches_per_solve"] = launches[name]
         kern[name]["share_of_solve"] = launches[name] * kern[name]["avg_ms"] * 1e-3 / sec
-    apply = time_apply(pi, plan, args.kernel_reps, bytes_per_cell["k_cg_step"] - 32)
+    apply = time_apply(pi, plan, args.kernel_reps, bytes_per_cell["code"])
     progress(f"operator apply y = M x: {apply['avg_ms'] * 1e3:.1f} us, {apply['achieved_GBs']:.0f} GB/s "
              f"at {apply['tile']} planes per segment")
     dom = max(kern, key=lambda k: kern[k]["launches_per_solve"] * kern[k]["avg_ms"])

@@ -293,15 +293,30 @@ pi_status pi_apply(pi_plan_t plan, int op, const void *x, void *y, void *stream)
 #define PI_K_OUTER 0   /* outer residual and update, Eq. ResidualMomentum      */
 #define PI_K_INNER 1   /* one inner CG iteration: the previous iteration's
                           correction and residual update, the new search
-                          direction and M p, in one pass                       */
+                          direction and M p, in one pass (for a plan with
+                          pi_get_cg_recompute = 1 the pass is two kernels,
+                          the interior and the boundary layers; both are
+                          timed)                                               */
 pi_status pi_time_kernel(pi_plan_t plan, int kernel, int32_t reps, double *avg_ms, void *stream);
+
+/*
+ * pi_get_cg_recompute -- 1 if the plan's inner CG passes (after the first
+ * of each outer step) evaluate q = M p_{k-1} again where they need it
+ * instead of storing q and reading it back, else 0 (also for NULL).  The
+ * iterates are the same bit for bit; a pass then moves 24 bytes per cell
+ * (reads r, p and the correction, writes them) instead of 32.  Chosen for
+ * 3-D FP32 CG plans without missing data at four cells per lane whose rows
+ * fit one wave strip (nx <= 256); it follows the tile, so read it after
+ * pi_set_tile or pi_autotune.
+ */
+int32_t pi_get_cg_recompute(pi_plan_t plan);
 
 /*
  * pi_autotune -- pick the tile (pi_set_tile) that minimises the time of one
  * outer step of Algorithm 1 for this plan: for each candidate (segment
  * length, cells per lane) it times the outer kernel once and the inner CG
- * pass `inner_iters` times
- * (pi_time_kernel, `reps` launches each), times the three fastest again with
+ * pass, with its finalize kernel where the tile needs one, `inner_iters`
+ * times (`reps` launches each), times the three fastest again with
  * 4 * reps launches and keeps the fastest of those; then it chooses between
  * plain and non-temporal streams in the outer kernel (4 * reps launches each).  Results are
  * cached per (ndim, dims, precision, inner solver) for the life of the process,

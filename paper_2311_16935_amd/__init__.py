@@ -95,6 +95,8 @@ def _load():
     lib.pi_get_tile.restype = ctypes.c_int32
     lib.pi_get_lane_cells.argtypes = [vp]
     lib.pi_get_lane_cells.restype = ctypes.c_int32
+    lib.pi_get_cg_recompute.argtypes = [vp]
+    lib.pi_get_cg_recompute.restype = ctypes.c_int32
     lib.pi_time_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(dbl), vp]
     lib.pi_time_kernel.restype = ctypes.c_int
     lib.pi_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp]
@@ -107,7 +109,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("pi_plan", "pi_plan_destroy", "pi_workspace_bytes", "pi_set_inner_iters", "pi_set_tile",
-            "pi_get_tile", "pi_get_lane_cells", "pi_solve", "pi_last_info",
+            "pi_get_tile", "pi_get_lane_cells", "pi_get_cg_recompute", "pi_solve", "pi_last_info",
             "pi_solve_batched", "pi_solve_batched_noalloc", "pi_source", "pi_apply", "pi_time_kernel", "pi_autotune", "pi_status_string")
 
 PI_K_OUTER, PI_K_INNER = 0, 1
@@ -177,6 +179,10 @@ def pi_get_tile(plan) -> int:
 
 def pi_get_lane_cells(plan) -> int:
     return int(lib.pi_get_lane_cells(plan))
+
+
+def pi_get_cg_recompute(plan) -> int:
+    return int(lib.pi_get_cg_recompute(plan))
 
 
 def pi_solve(plan, gx, gy, gz, P, tol, max_iter, flags=0, stream=None):

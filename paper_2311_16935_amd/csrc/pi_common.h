@@ -38,6 +38,18 @@ constexpr int kShapeCC = 12;
 // (256^3) to 4 % (2048^2) faster without it; at 2048 blocks 5-14 % slower.
 constexpr int kInlineMaxBlocks = 1024;
 constexpr int32_t kNoStop = 1 << 30;
+
+// CG passes that evaluate q again (k_cg_rq): the layers next to the y faces
+// (rows 0..2 and ny-3..ny-1, every plane, in chunks of kRqChunk planes) and
+// next to the march faces (planes 0..2 and nm-3..nm-1 of the other rows) are
+// wave tasks of blocks of their own; the rest is interior.  With ny or nm
+// below 7 there is no interior and every row is a boundary row.
+constexpr int kRqChunk = 4;
+__host__ __device__ inline int64_t rq_ntasks(int ny, int nm) {
+  const bool inner = ny >= 7 && nm >= 7;
+  const int64_t nA = (int64_t)(inner ? 6 : ny) * ((nm + kRqChunk - 1) / kRqChunk);
+  return nA + (inner ? 2 * (int64_t)(ny - 6) : 0);
+}
 constexpr int kShapeCC4 = 13;
 
 // Launch shape of an instance: (3-D) + 2 * (lane width: 0 for one cell, 1
@@ -129,6 +141,10 @@ struct Inst {
                     // pass's partials themselves (no finalize kernel)
   int32_t nt_outer; // the outer kernel streams S, P' and r non-temporally
                     // (chosen by the autotuner)
+  int32_t cg_rq;    // host side: the plan's CG passes evaluate q again
+                    // instead of storing it (launch_cg_rq)
+  int32_t cg_slots; // partial-sum slots of a CG pass: nblocks, plus the
+                    // boundary-layer blocks of k_cg_rq
   int32_t ncomp;    // connected groups of data cells
   int32_t inner_iters; // inner Krylov iterations per outer step
   int32_t inner_op; // operator of the inner solve: 0 [W^{n+1}], 1 [W^{n+1}] - [W^n]

@@ -542,7 +542,7 @@ __device__ inline void cg_partials(const Inst &in, const double *part, int j, do
       reinterpret_cast<const double2 *>(part + ((int64_t)(1 + (j & 1)) * in.part_stride + in.part_base) * 4);
 #pragma unroll
   for (int k = 0; k < 4; ++k) s[k] = 0.0;
-  for (int i = threadIdx.x; i < in.nblocks; i += kBlock) {
+  for (int i = threadIdx.x; i < in.cg_slots; i += kBlock) {
     const double2 a = slots[2 * i], b = slots[2 * i + 1];
     s[0] += a.x;
     s[1] += a.y;
@@ -1083,6 +1083,388 @@ __global__ __launch_bounds__(kBlock) void k_cg_step(const BlockEnt *tab, const I
 }
 
 // ---------------------------------------------------------------------------
+// The inner CG pass without a stored q: 3-D grids without missing data whose
+// rows fit one wave strip (four cells per lane), FP32.
+//
+// CG's state is r, p and the correction; q = A p is stored only so that the
+// next pass can form r_k = r_{k-1} - alpha q_{k-1}.  Here q_{k-1} = A p_{k-1}
+// is evaluated again where it is needed: p_k at the cell and at its six
+// neighbours needs A p_{k-1} there, so p_{k-1} is read within two cells (rows
+// y-2 .. y+2 of plane m, rows y-1 .. y+1 of planes m-1 .. m+1, row y of planes
+// m-2 .. m+2; the rows off the wave's own come from L2) and r_{k-1} within
+// one.  Per cell a pass reads r, p and d and writes r', p' and d: 24 bytes
+// instead of 32.  A p_{k-1} is formed with the operator and operand values
+// the previous pass used for q_{k-1}, in the same order, so r_k, p_k and the
+// sums are those of the stored-q pass bit for bit.  The first pass of an
+// outer step (k_cg_first) is unchanged.
+//
+// Work is split by where the counter codes are constant: the planes 3 ..
+// nm-4 of rows 3 .. ny-4 of every wave strip, where every code a pass looks
+// at depends on x alone, so each lane keeps the weights of its cells in
+// registers (no table, no validity tests: rq_int_march), and the rest, the
+// layers next to the y and march faces, as short wave tasks with per-cell
+// codes and the weight table (rq_bnd_march) in blocks of their own.  One
+// kernel does both (k_cg_rq).
+// ---------------------------------------------------------------------------
+
+// Per-direction weights of the operator at a cell of code cd, as apply_m
+// ([W^{n+1}], from the state table) or apply_l (the fixed point's operator)
+// take them.
+template <typename T, bool OPL, class Lut>
+__device__ inline void op_weights(Lut lut, const T *wi, const T *a, uint32_t cd, T (&w)[6]) {
+  const bool all = cd == interior_code<3>();
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    if constexpr (OPL) w[d] = (all || dstate(cd, d, 5)) ? a[d] : T(0);
+    else w[d] = all ? wi[d] : lut(d, dstate(cd, d, 5));
+  }
+}
+// The stencil with given weights: the operations of apply_m / apply_l in
+// their order.
+template <typename T, bool OPL>
+__device__ inline T op_w(const T (&w)[6], T vC, T vW, T vE, T vN, T vS, T vB, T vF) {
+  if constexpr (OPL) {
+    T s = T(0);
+    s += w[DE] * (vC - vE);
+    s += w[DW] * (vC - vW);
+    s += w[DN] * (vC - vN);
+    s += w[DS] * (vC - vS);
+    s += w[DF] * (vC - vF);
+    s += w[DB] * (vC - vB);
+    return s;
+  } else {
+    T s = vC;
+    s -= w[DE] * vE;
+    s -= w[DW] * vW;
+    s -= w[DN] * vN;
+    s -= w[DS] * vS;
+    s -= w[DF] * vF;
+    s -= w[DB] * vB;
+    return s;
+  }
+}
+
+// x neighbours of a lane's W cells; the strip is the whole row, so beyond
+// its ends lies the grid face (0)
+template <typename T, int W>
+__device__ inline void xnb0(const Vec<T, W> &v, int lane, T (&vW)[W], T (&vE)[W]) {
+  T left = __shfl_up(v.e[W - 1], 1, kWave);
+  T right = __shfl_down(v.e[0], 1, kWave);
+  if (lane == 0) left = T(0);
+  if (lane == kWave - 1) right = T(0);
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    vW[k] = k == 0 ? left : v.e[k > 0 ? k - 1 : 0];
+    vE[k] = k == W - 1 ? right : v.e[k + 1 < W ? k + 1 : 0];
+  }
+}
+
+// The interior planes of a wave: [i0, i1), empty unless the
+// row is at least three rows from both y faces.
+__device__ inline void rq_split(const Walk &wk, int &i0, int &i1) {
+  i0 = i1 = wk.m0;
+  if (wk.row >= 3 && wk.row + 4 <= wk.ny) {
+    const int a = max(wk.m0, 3), b = min(wk.m1, wk.nm - 3);
+    if (a < b) {
+      i0 = a;
+      i1 = b;
+    }
+  }
+}
+
+template <int W, bool OPL>
+__device__ inline void rq_int_march(const Inst &in, const CgPass<float> &cg, const Walk &wk, double (&acc)[4]) {
+  using T = float;
+  int i0, i1;
+  rq_split(wk, i0, i1);
+  if (i0 < i1) {  // uniform over the wave
+    const int lane = threadIdx.x & 63;
+    const T al = cg.al, be = cg.be;
+    // weights of this lane's cells: their codes depend on x alone here
+    T wc[W][6];
+    {
+      T wi[6], a[6];
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        wi[d] = (T)in.lut_np1[d][interior_state<3>()];
+        a[d] = (T)in.a[d];
+      }
+      auto lut = [&](int d, int st) { return (T)in.lut_np1[d][st]; };
+#pragma unroll
+      for (int k = 0; k < W; ++k)
+        op_weights<T, OPL>(lut, wi, a, code_at<3>(min(wk.x + k, wk.nx - 1), 3, 3, wk.nx, wk.ny, wk.nz), wc[k]);
+    }
+    auto opv = [&](const Vec<T, W> &v, const Vec<T, W> &vN, const Vec<T, W> &vS, const Vec<T, W> &vB,
+                   const Vec<T, W> &vF) {
+      T w[W], e[W];
+      xnb0<T, W>(v, lane, w, e);
+      Vec<T, W> o;
+#pragma unroll
+      for (int k = 0; k < W; ++k) o.e[k] = op_w<T, OPL>(wc[k], v.e[k], w[k], e[k], vN.e[k], vS.e[k], vB.e[k], vF.e[k]);
+      return o;
+    };
+    const PI_G T *R = cg.rold, *Pp = cg.pold;
+    const int64_t sm = wk.sm, sy = wk.nx;
+    auto at = [&](int j) { return wk.base + (int64_t)j * sm; };
+    // window at m = i0 (rows y-2 .. y+2 and planes i0-2 .. i0+2 are in the grid)
+    Vec<T, W> P0a = ldv<W>(Pp, at(i0)), P0b = ldv<W>(Pp, at(i0 + 1));
+    Vec<T, W> Pn0 = ldv<W>(Pp, at(i0 - 1) + sy), Pn1 = ldv<W>(Pp, at(i0) + sy);
+    Vec<T, W> Ps0 = ldv<W>(Pp, at(i0 - 1) - sy), Ps1 = ldv<W>(Pp, at(i0) - sy);
+    Vec<T, W> Um1, U0, rk0;
+    {
+      const Vec<T, W> Pm1 = ldv<W>(Pp, at(i0 - 1)), Pm2 = ldv<W>(Pp, at(i0 - 2));
+      const Vec<T, W> Rm1 = ldv<W>(R, at(i0 - 1)), R0 = ldv<W>(R, at(i0));
+      const Vec<T, W> Am1 = opv(Pm1, Pn0, Ps0, Pm2, P0a);
+      const Vec<T, W> A0 = opv(P0a, Pn1, Ps1, Pm1, P0b);
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        Um1.e[k] = (Rm1.e[k] - al * Am1.e[k]) + be * Pm1.e[k];
+        rk0.e[k] = R0.e[k] - al * A0.e[k];
+        U0.e[k] = rk0.e[k] + be * P0a.e[k];
+      }
+    }
+    // inputs of step m, fetched during step m - 1
+    struct In {
+      Vec<T, W> p2, pn1, ps1, pnn, pss, ry1, rn, rs, d;  // P(y, m+2), P(y+-1, m+1), P(y+-2, m), R(y, m+1), R(y+-1, m), d(y, m)
+    };
+    auto fetch = [&](int m, In &f) {
+      const int64_t c0 = at(m), c1 = at(m + 1);
+      f.p2 = ldv<W>(Pp, at(m + 2));
+      f.pn1 = ldv<W>(Pp, c1 + sy);
+      f.ps1 = ldv<W>(Pp, c1 - sy);
+      f.pnn = ldv<W>(Pp, c0 + 2 * sy);
+      f.pss = ldv<W>(Pp, c0 - 2 * sy);
+      f.ry1 = ldv<W>(R, c1);
+      f.rn = ldv<W>(R, c0 + sy);
+      f.rs = ldv<W>(R, c0 - sy);
+      f.d = cg.rd_d ? ldv_nt<W>(cg.d, c0) : vzero<T, W>();
+    };
+    In cur, nxt;
+    fetch(i0, cur);
+    for (int m = i0; m < i1; ++m) {
+      if (m + 1 < i1) fetch(m + 1, nxt);  // uniform over the wave
+      // A p_{k-1} where p_k is needed: (y, m+1), (y+1, m), (y-1, m)
+      const Vec<T, W> Ay1 = opv(P0b, cur.pn1, cur.ps1, P0a, cur.p2);
+      const Vec<T, W> An = opv(Pn1, cur.pnn, P0a, Pn0, cur.pn1);
+      const Vec<T, W> As = opv(Ps1, P0a, cur.pss, Ps0, cur.ps1);
+      Vec<T, W> U1, Un, Us, rk1;
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        rk1.e[k] = cur.ry1.e[k] - al * Ay1.e[k];
+        U1.e[k] = rk1.e[k] + be * P0b.e[k];
+        Un.e[k] = (cur.rn.e[k] - al * An.e[k]) + be * Pn1.e[k];
+        Us.e[k] = (cur.rs.e[k] - al * As.e[k]) + be * Ps1.e[k];
+      }
+      const Vec<T, W> q = opv(U0, Un, Us, Um1, U1);  // q_k = A p_k
+      Vec<T, W> dv;
+#pragma unroll
+      for (int k = 0; k < W; ++k) dv.e[k] = cur.d.e[k] + al * P0a.e[k];
+      if (wk.act) {
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          const double r = (double)rk0.e[k], qd = (double)q.e[k];
+          acc[0] += (double)U0.e[k] * qd;
+          acc[1] += r * qd;
+          acc[2] += qd * qd;
+          acc[3] += r * r;
+        }
+        const int64_t c = at(m);
+        stv_nt<W>(cg.pnew, c, U0);
+        stv_nt<W>(cg.rnew, c, rk0);
+        if (cg.wr_d) stv_nt<W>(cg.d, c, dv);
+      }
+      Um1 = U0;
+      U0 = U1;
+      rk0 = rk1;
+      P0a = P0b;
+      P0b = cur.p2;
+      Pn0 = Pn1;
+      Pn1 = cur.pn1;
+      Ps0 = Ps1;
+      Ps1 = cur.ps1;
+      cur = nxt;
+    }
+  }
+}
+
+// The boundary layers: planes [a, b) of the wave, every operand and code
+// checked.
+template <int W, bool OPL>
+__device__ inline void rq_bnd_march(const Inst &in, const CgPass<float> &cg, const Walk &wk, const float (*lut)[kStates],
+                                    const float *wi, const float *a, int a0, int a1, double (&acc)[4]) {
+  using T = float;
+  if (a0 >= a1) return;  // uniform over the wave
+  const int lane = threadIdx.x & 63;
+  const T al = cg.al, be = cg.be;
+  const int nm = wk.nm;
+  const int64_t sm = wk.sm, sy = wk.nx;
+  // rows y +- 1, y +- 2; a row outside the grid reads the wave's own row and is zeroed
+  const bool hN1 = wk.row + 1 < wk.ny, hS1 = wk.row > 0, hN2 = wk.row + 2 < wk.ny, hS2 = wk.row > 1;
+  const int64_t oN1 = hN1 ? sy : 0, oS1 = hS1 ? -sy : 0, oN2 = hN2 ? 2 * sy : 0, oS2 = hS2 ? -2 * sy : 0;
+  const PI_G T *R = cg.rold, *Pp = cg.pold;
+  const Vec<T, W> z = vzero<T, W>();
+  // plane j, clamped into the grid; planes outside read as 0
+  auto cj = [&](int j) { return wk.base + (int64_t)min(max(j, 0), nm - 1) * sm; };
+  auto inp = [&](int j) { return j >= 0 && j < nm; };
+  auto ldz = [&](const PI_G T *arr, int64_t c, bool ok) { return ok ? ldv<W>(arr, c) : z; };
+  auto codes = [&](int j, int row) {
+    Vec<uint32_t, W> v;
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+      v.e[k] = code_at<3>(min(wk.x + k, wk.nx - 1), row, min(max(j, 0), nm - 1), wk.nx, wk.ny, wk.nz);
+    return v;
+  };
+  auto tl = [&](int d, int st) { return lut[d][st]; };
+  auto opv = [&](const Vec<uint32_t, W> &cd, const Vec<T, W> &v, const Vec<T, W> &vN, const Vec<T, W> &vS,
+                 const Vec<T, W> &vB, const Vec<T, W> &vF) {
+    T w[W], e[W];
+    xnb0<T, W>(v, lane, w, e);
+    Vec<T, W> o;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      T wt[6];
+      op_weights<T, OPL>(tl, wi, a, cd.e[k], wt);
+      o.e[k] = op_w<T, OPL>(wt, v.e[k], w[k], e[k], vN.e[k], vS.e[k], vB.e[k], vF.e[k]);
+    }
+    return o;
+  };
+  // p_k = (r - al A p) + be p at in-grid cells, else 0; r_k likewise
+  auto pk = [&](bool ok, const Vec<T, W> &r, const Vec<T, W> &Ap, const Vec<T, W> &p, Vec<T, W> &rk) {
+    Vec<T, W> u;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      rk.e[k] = ok ? r.e[k] - al * Ap.e[k] : T(0);
+      u.e[k] = ok ? rk.e[k] + be * p.e[k] : T(0);
+    }
+    return u;
+  };
+  Vec<T, W> P0a = ldz(Pp, cj(a0), true), P0b = ldz(Pp, cj(a0 + 1), inp(a0 + 1));
+  Vec<T, W> Pn0 = ldz(Pp, cj(a0 - 1) + oN1, hN1 && inp(a0 - 1)), Pn1 = ldz(Pp, cj(a0) + oN1, hN1);
+  Vec<T, W> Ps0 = ldz(Pp, cj(a0 - 1) + oS1, hS1 && inp(a0 - 1)), Ps1 = ldz(Pp, cj(a0) + oS1, hS1);
+  Vec<T, W> Um1, U0, rk0, t;
+  {
+    const Vec<T, W> Pm1 = ldz(Pp, cj(a0 - 1), inp(a0 - 1)), Pm2 = ldz(Pp, cj(a0 - 2), inp(a0 - 2));
+    const Vec<T, W> Am1 = opv(codes(a0 - 1, wk.row), Pm1, Pn0, Ps0, Pm2, P0a);
+    Um1 = pk(inp(a0 - 1), ldz(R, cj(a0 - 1), inp(a0 - 1)), Am1, Pm1, t);
+    const Vec<T, W> A0 = opv(codes(a0, wk.row), P0a, Pn1, Ps1, Pm1, P0b);
+    U0 = pk(true, ldz(R, cj(a0), true), A0, P0a, rk0);
+  }
+  for (int m = a0; m < a1; ++m) {
+    const int64_t c0 = cj(m), c1 = cj(m + 1);
+    const Vec<T, W> P0c = ldz(Pp, cj(m + 2), inp(m + 2));
+    const Vec<T, W> Pn2 = ldz(Pp, c1 + oN1, hN1 && inp(m + 1)), Ps2 = ldz(Pp, c1 + oS1, hS1 && inp(m + 1));
+    const Vec<T, W> Pnn = ldz(Pp, c0 + oN2, hN2), Pss = ldz(Pp, c0 + oS2, hS2);
+    Vec<T, W> rk1;
+    const Vec<T, W> Ay1 = opv(codes(m + 1, wk.row), P0b, Pn2, Ps2, P0a, P0c);
+    const Vec<T, W> U1 = pk(inp(m + 1), ldz(R, c1, inp(m + 1)), Ay1, P0b, rk1);
+    const Vec<T, W> An = opv(codes(m, wk.row + 1), Pn1, Pnn, P0a, Pn0, Pn2);
+    const Vec<T, W> Un = pk(hN1, ldz(R, c0 + oN1, hN1), An, Pn1, t);
+    const Vec<T, W> As = opv(codes(m, wk.row - 1), Ps1, P0a, Pss, Ps0, Ps2);
+    const Vec<T, W> Us = pk(hS1, ldz(R, c0 + oS1, hS1), As, Ps1, t);
+    const Vec<T, W> q = opv(codes(m, wk.row), U0, Un, Us, Um1, U1);
+    const Vec<T, W> d = cg.rd_d ? ldv_nt<W>(cg.d, c0) : z;
+    Vec<T, W> dv;
+#pragma unroll
+    for (int k = 0; k < W; ++k) dv.e[k] = d.e[k] + al * P0a.e[k];
+    if (wk.act) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        const double r = (double)rk0.e[k], qd = (double)q.e[k];
+        acc[0] += (double)U0.e[k] * qd;
+        acc[1] += r * qd;
+        acc[2] += qd * qd;
+        acc[3] += r * r;
+      }
+      stv_nt<W>(cg.pnew, c0, U0);
+      stv_nt<W>(cg.rnew, c0, rk0);
+      if (cg.wr_d) stv_nt<W>(cg.d, c0, dv);
+    }
+    Um1 = U0;
+    U0 = U1;
+    rk0 = rk1;
+    P0a = P0b;
+    P0b = P0c;
+    Pn0 = Pn1;
+    Pn1 = Pn2;
+    Ps0 = Ps1;
+    Ps1 = Ps2;
+  }
+}
+
+// Boundary-layer task t (rq_ntasks of them) -> row and planes [a, b): the
+// rows next to the y faces in chunks of kRqChunk planes, then for every
+// other row the three planes next to each march face; false past the last.
+__device__ inline bool rq_task(const Inst &in, int64_t t, int &row, int &a, int &b) {
+  const int ny = in.ny, nm = in.nm;
+  const bool inner = ny >= 7 && nm >= 7;
+  const int nbr = inner ? 6 : ny;
+  const int nch = (nm + kRqChunk - 1) / kRqChunk;
+  const int64_t nA = (int64_t)nbr * nch;
+  if (t < nA) {
+    const int i = (int)(t / nch), c = (int)(t % nch);
+    row = inner ? (i < 3 ? i : ny - 6 + i) : i;
+    a = c * kRqChunk;
+    b = min(nm, a + kRqChunk);
+    return true;
+  }
+  t -= nA;
+  if (!inner || t >= 2 * (int64_t)(ny - 6)) return false;
+  row = 3 + (int)(t / 2);
+  a = (t % 2 == 0) ? 0 : nm - 3;
+  b = a + 3;
+  return true;
+}
+
+// A wave's view of a task: the one strip of row `row`, planes [m0, m1).
+template <int W>
+__device__ inline Walk rq_walk(const Inst &in, int row, int m0, int m1) {
+  Walk k;
+  k.sm = in.sm;
+  k.code = gp<uint32_t>(in.code);
+  k.nm = in.nm;
+  k.nx = in.nx;
+  k.ny = in.ny;
+  k.nz = in.nz;
+  k.x = (threadIdx.x & 63) * W;
+  k.m0 = m0;
+  k.m1 = m1;
+  k.row = row;
+  k.act = k.x < in.nx;
+  k.base = (int64_t)min(k.x, in.nx - W) + (int64_t)row * in.srow;
+  return k;
+}
+
+// One CG pass.  Blocks 0 .. nblocks-1 of the instance march the interior
+// planes of their strips and segments; the blocks after them (first in the
+// launch's table, so dispatched first) take one boundary-layer task per wave.
+template <int W, bool OPL>
+__global__ __launch_bounds__(kBlock) void k_cg_rq(const BlockEnt *tab, const Inst *__restrict__ insts,
+                                                 State *__restrict__ sts, double *part, int kpass) {
+  using T = float;
+  PI_PROLOGUE
+  const CgPass<T> cg = cg_pass<T>(in, st, part, e.lb, kpass);
+  if (cg.skip) return;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (e.lb < in.nblocks) {  // uniform over the block
+    rq_int_march<W, OPL>(in, cg, make_walk<W>(in, e.lb), acc);
+  } else {
+    __shared__ T lut[6][kStates];
+    load_lut<T>(in.lut_np1, lut);
+    T wi[6], a[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      wi[d] = (T)in.lut_np1[d][interior_state<3>()];
+      a[d] = (T)in.a[d];
+    }
+    int row, a0, a1;
+    const int64_t t = (int64_t)(e.lb - in.nblocks) * kWavesPerBlock + (threadIdx.x >> 6);
+    if (rq_task(in, t, row, a0, a1))  // uniform over the wave
+      rq_bnd_march<W, OPL>(in, cg, rq_walk<W>(in, row, a0, a1), lut, wi, a, a0, a1, acc);
+  }
+  publish<4>(in, cg_part(in, part, kpass), e.lb, acc);
+}
+
+// ---------------------------------------------------------------------------
 // inner BiCGStab on M delta = r (shadow residual = the outer residual)
 // ---------------------------------------------------------------------------
 // phase 1: p <- r + beta (p - omega v) (p <- r first), v' <- M p (into q), rhat.v'
@@ -1370,8 +1752,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const Inst *__restrict__ in
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   // slots are 32 bytes: load them as double2 pairs, several rounds in flight
   const double2 *slots = reinterpret_cast<const double2 *>(part + (int64_t)in.part_base * 4);
+  const int nslots = kind == K_CG_STEP ? in.cg_slots : in.nblocks;
 #pragma unroll 8
-  for (int i = threadIdx.x; i < in.nblocks; i += kBlock) {
+  for (int i = threadIdx.x; i < nslots; i += kBlock) {
     const double2 a = slots[2 * i], b = slots[2 * i + 1];
     s[0] += a.x;
     s[1] += a.y;
@@ -2012,6 +2395,21 @@ static hipError_t launch_t(KernelId k, int shape, const LaunchArgs &la) {
 hipError_t launch(KernelId k, bool fp64, int shape, const LaunchArgs &la) {
   if (la.nblocks <= 0) return hipSuccess;
   return fp64 ? launch_t<double>(k, shape, la) : launch_t<float>(k, shape, la);
+}
+
+hipError_t launch_cg_rq(bool opl, const LaunchArgs &la) {
+  if (la.nblocks <= 0) return hipSuccess;
+  const dim3 grid(la.nblocks), block(kBlock);
+  const BlockEnt *tab = la.tab;
+  const Inst *insts = la.insts;
+  State *sts = la.sts;
+  double *part = la.part;
+  hipStream_t s = la.stream;
+  if (opl)
+    k_cg_rq<4, true><<<grid, block, 0, s>>>(PI_ARGS, la.iarg);
+  else
+    k_cg_rq<4, false><<<grid, block, 0, s>>>(PI_ARGS, la.iarg);
+  return hipGetLastError();
 }
 
 bool reduces(KernelId k) {

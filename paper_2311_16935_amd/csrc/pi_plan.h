@@ -50,6 +50,8 @@ struct pi_plan_s {
   pi::BlockEnt *d_tab = nullptr;
   double *d_part = nullptr;
   int ntab = 0;
+  pi::BlockEnt *d_tab_rq = nullptr;  // CG passes of a cg_rq plan: boundary-layer blocks, then d_tab's
+  int ntab_rq = 0;
   pi::State *h_state = nullptr;    // pinned mirror
   hipGraphExec_t graph = nullptr;  // cached outer-step graph
   int graph_key = -1;

@@ -431,26 +431,54 @@ static int32_t components(const pi_plan_s *p, const uint8_t *mask, std::vector<i
 // plan's current strip decomposition.
 hipError_t plan_tables(pi_plan_s *p) {
   if (p->d_tab) (void)hipFree(p->d_tab);
+  if (p->d_tab_rq) (void)hipFree(p->d_tab_rq);
   if (p->d_part) (void)hipFree(p->d_part);
   p->d_tab = nullptr;
+  p->d_tab_rq = nullptr;
   p->d_part = nullptr;
   p->ntab = 0;  // no table until the new one is in place
+  p->ntab_rq = 0;
   std::vector<Inst *> one{&p->inst};
   int parts = 0;
   std::vector<BlockEnt> tab = build_table(one, 0, &parts);
   // three partial-sum arrays: the outer-step kernels', and one per parity
   // of the inner CG passes
-  p->inst.part_stride = parts;
-  p->inst.cg_inline = p->inst.nblocks <= kInlineMaxBlocks ? 1 : 0;
+  // CG passes without a stored q: 3-D, no missing data, FP32, four cells per
+  // lane and one wave strip per row.  Their boundary-layer blocks come first
+  // in the CG passes' table (dispatched first, they run beside the interior
+  // blocks) and have partial-sum slots of their own after the others.
+  p->inst.cg_rq = (p->ndim == 3 && p->inst.gen && !p->fp64 && !p->bicgstab && !p->cc && p->inst.vw == 4 &&
+                   p->inst.nxs == 1)
+                      ? 1
+                      : 0;
+  const int nbnd =
+      p->inst.cg_rq ? (int)((rq_ntasks(p->inst.ny, p->inst.nm) + kWavesPerBlock - 1) / kWavesPerBlock) : 0;
+  p->inst.cg_slots = p->inst.nblocks + nbnd;
+  p->inst.part_stride = std::max(parts, p->inst.cg_slots);
+  p->inst.cg_inline = p->inst.cg_slots <= kInlineMaxBlocks ? 1 : 0;
+  std::vector<BlockEnt> tab_rq;
+  if (p->inst.cg_rq) {
+    for (int j = 0; j < nbnd; ++j) tab_rq.push_back(BlockEnt{0, p->inst.nblocks + j});
+    tab_rq.insert(tab_rq.end(), tab.begin(), tab.end());
+  }
   hipError_t e = hipMalloc((void **)&p->d_tab, tab.size() * sizeof(BlockEnt));
-  if (e == hipSuccess) e = hipMalloc((void **)&p->d_part, (size_t)std::max(parts, 1) * 3 * 4 * sizeof(double));
+  if (e == hipSuccess)
+    e = hipMalloc((void **)&p->d_part, (size_t)std::max(p->inst.part_stride, 1) * 3 * 4 * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(p->d_tab, tab.data(), tab.size() * sizeof(BlockEnt), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !tab_rq.empty()) {
+    e = hipMalloc((void **)&p->d_tab_rq, tab_rq.size() * sizeof(BlockEnt));
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_tab_rq, tab_rq.data(), tab_rq.size() * sizeof(BlockEnt), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) {
     p->ntab = (int)tab.size();
+    p->ntab_rq = (int)tab_rq.size();
   } else {
     if (p->d_tab) (void)hipFree(p->d_tab);
+    if (p->d_tab_rq) (void)hipFree(p->d_tab_rq);
     if (p->d_part) (void)hipFree(p->d_part);
     p->d_tab = nullptr;
+    p->d_tab_rq = nullptr;
     p->d_part = nullptr;
   }
   return e;
@@ -675,7 +703,7 @@ extern "C" void pi_plan_destroy(pi_plan_t p) {
   void *ptrs[] = {p->code, p->label, p->comp_inv, p->comp_sum, p->comp_order, p->seg_begin, p->comp_seg,
                   p->seg_sum, p->P[0], p->P[1], p->S64, p->res, p->q, p->res1, p->q1,
                   p->d, p->p[0], p->p[1], p->bs[0], p->bs[1], p->bs[2], p->bs[3], p->d_inst, p->d_state,
-                  p->d_tab, p->d_part};
+                  p->d_tab, p->d_tab_rq, p->d_part};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   if (p->h_state) (void)hipHostFree(p->h_state);

@@ -41,6 +41,9 @@ struct Launcher {
   double *part = nullptr;
   int count = 0;             // instances
   bool cg_finalize = false;  // some instance's CG passes need the finalize kernel
+  bool cg_rq = false;        // single plan whose CG passes evaluate q again
+  bool cg_rq_opl = false;    // ... with the fixed point's operator
+  Group rq;                  // ... and the table of its CG passes
   Group grp[kShapes];
 
   // the kernel over every instance, then (if it reduces) its finalize; the
@@ -50,8 +53,16 @@ struct Launcher {
                 bool finalize = true) const {
     for (int g = 0; g < kShapes; ++g) {
       if (grp[g].ntab <= 0) continue;
-      LaunchArgs la{grp[g].tab, insts, sts, part, grp[g].ntab, s, iarg, x, y};
-      hipError_t e = launch(k, fp64, g, la);
+      hipError_t e;
+      if (k == K_CG_STEP && cg_rq) {
+        // every CG pass over the table with the boundary-layer blocks, so
+        // that all of a pass's partial-sum slots are written
+        LaunchArgs la{rq.tab, insts, sts, part, rq.ntab, s, iarg, x, y};
+        e = iarg > 0 ? launch_cg_rq(cg_rq_opl, la) : launch(k, fp64, g, la);
+      } else {
+        LaunchArgs la{grp[g].tab, insts, sts, part, grp[g].ntab, s, iarg, x, y};
+        e = launch(k, fp64, g, la);
+      }
       if (e != hipSuccess) return e;
     }
     if (k == K_CG_STEP && !cg_finalize) return hipSuccess;
@@ -238,6 +249,9 @@ Launcher single_launcher(pi_plan_s *p) {
   L.part = p->d_part;
   L.count = 1;
   L.cg_finalize = !p->bicgstab && !p->inst.cg_inline;
+  L.cg_rq = p->inst.cg_rq != 0 && p->d_tab_rq != nullptr;
+  L.cg_rq_opl = p->inst.inner_op != 0;
+  L.rq = Group{p->d_tab_rq, p->ntab_rq};
   L.grp[shape_of(p->ndim, p->inst.vw, p->inst.gen, p->inst.cc)] = Group{p->d_tab, p->ntab};
   return L;
 }
@@ -410,6 +424,7 @@ pi_status batch_setup(int64_t count, const pi_plan_t *plans, const void *const *
   b.cg_finalize = false;
   for (auto &h : b.host) {
     h.part_stride = b.parts;
+    h.cg_slots = h.nblocks;  // batched launches store q
     h.cg_inline = h.nblocks <= kInlineMaxBlocks ? 1 : 0;
     if (!b.bicg && !h.cg_inline) b.cg_finalize = true;
   }
@@ -722,8 +737,8 @@ pi_status timing_state(pi_plan_t p, hipStream_t stream) {
   st.alpha = 1e-3;
   st.beta = 0.5;
   st.normS2 = 1.0;
-  std::vector<double> slots((size_t)p->inst.nblocks * 4);
-  for (int i = 0; i < p->inst.nblocks; ++i) {
+  std::vector<double> slots((size_t)p->inst.cg_slots * 4);
+  for (int i = 0; i < p->inst.cg_slots; ++i) {
     slots[4 * i + 0] = 1e3;  // p.q
     slots[4 * i + 1] = 0.0;  // r.q
     slots[4 * i + 2] = 0.0;  // q.q
@@ -761,21 +776,22 @@ out:
   return rc;
 }
 
-// Per-pass cost of the CG finalize kernel for the plan's current table
-// (zero when its CG passes sum the partials themselves): back-to-back
-// launches, so the gap between kernels is included as in a solve.
-pi_status time_cg_finalize(pi_plan_t p, int32_t reps, double *avg_ms, hipStream_t stream) {
-  *avg_ms = 0.0;
-  if (p->bicgstab || p->inst.cg_inline) return PI_OK;
+// Per-pass cost of an inner CG pass as a solve runs it: the pass and, for
+// an instance of many blocks, its finalize kernel, launched back to back
+// (the finalize waits for the pass to drain, as it does in a solve).  The
+// finalize moves the state on between launches; the values do not change
+// the amount of work.
+pi_status time_cg_pass(pi_plan_t p, int32_t reps, double *avg_ms, hipStream_t stream) {
   pi_status rc = timing_state(p, stream);
   if (rc != PI_OK) return rc;
+  const Launcher L = single_launcher(p);
   const int kpass = 2;
-  return time_launches(stream, reps, avg_ms, [&] {
-    return launch_finalize(K_CG_STEP, p->d_inst, p->d_state, p->d_part, 1, stream, kpass);
-  });
+  return time_launches(stream, reps, avg_ms, [&] { return L.go(K_CG_STEP, stream, kpass, nullptr, nullptr, true); });
 }
 
 }  // namespace
+
+extern "C" int32_t pi_get_cg_recompute(pi_plan_t p) { return p && p->inst.cg_rq ? 1 : 0; }
 
 extern "C" pi_status pi_time_kernel(pi_plan_t p, int kernel, int32_t reps, double *avg_ms, void *stream_) {
   if (!p || !avg_ms || reps < 1 || (kernel != PI_K_OUTER && kernel != PI_K_INNER)) return PI_ERR_INVALID_ARG;
@@ -824,12 +840,11 @@ extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, v
     auto step_ms = [&](const std::array<int32_t, 2> &c, int32_t r, double *ms) -> pi_status {
       pi_status e;
       if ((e = pi_set_tile(p, c[0], c[1])) != PI_OK) return e;
-      double t_outer = 0.0, t_inner = 0.0, t_fin = 0.0;
+      double t_outer = 0.0, t_inner = 0.0;
       if ((e = pi_time_kernel(p, PI_K_OUTER, r, &t_outer, stream)) != PI_OK ||
-          (!p->bicgstab && (e = pi_time_kernel(p, PI_K_INNER, r, &t_inner, stream)) != PI_OK) ||
-          (e = time_cg_finalize(p, r, &t_fin, (hipStream_t)stream)) != PI_OK)
+          (!p->bicgstab && (e = time_cg_pass(p, r, &t_inner, (hipStream_t)stream)) != PI_OK))
         return e;
-      *ms = t_outer + p->inner_iters * (t_inner + t_fin);
+      *ms = t_outer + p->inner_iters * t_inner;
       return PI_OK;
     };
     // every candidate once, then the three fastest again with four times the

@@ -452,11 +452,48 @@ def test_fixed_point_cg_variant_reaches_the_same_field(name, make, fp64):
 
 
 @pytest.mark.parametrize("fixed_point", [False, True], ids=["paper_iteration", "fixed_point_variant"])
-def test_many_block_grid_takes_alpha_and_beta_from_a_finalize_kernel(fixed_point):
+@pytest.mark.parametrize("dims", [(40, 23, 17), (32, 5, 6), (256, 9, 8)], ids=["interior_and_layers", "layers_only",
+                                                                              "full_strip"])
+def test_cg_passes_that_evaluate_q_again(dims, fixed_point):
+    """3-D FP32 grids without missing data at four cells per lane, rows of at
+    most 256 cells: the CG passes after the first evaluate q = M p again
+    instead of reading it (an interior kernel and a boundary-layer kernel).
+    The converged field must match the oracle's fixed point; (32, 5, 6) has
+    no interior rows or planes, so the boundary kernel does all the work."""
+    import paper_2311_16935_amd as pi
+    from oracle.solve import fixed_point_cg
+
+    announce("q evaluated again", dims, fixed_point)
+    w = synth.random_small(83, 3, dims, anisotropic=True, mask_frac=0.0)
+    g = _grads(w, False)
+    plan = pi.Plan(w.dims, w.spacing, fixed_point=fixed_point)
+    pi.pi_set_tile(plan.handle, 4, 4)
+    assert pi.pi_get_cg_recompute(plan.handle) == 1
+    res = plan.solve(g, tol=1e-9, max_iter=200000)
+    assert res.status == 0, res.info
+    sys_ = oracle_for(w)
+    ref = fixed_point_cg(sys_, sys_.source([np_(x).astype(np.float64) for x in g]), rtol=1e-13).P
+    err = rel_maxabs(np_(res.P).astype(np.float64).ravel(), ref)
+    print(f"q evaluated again {dims}: outer {res.info['outer_iters']}, err {err:.2e}")
+    assert err <= 1e-5, err
+    # the same plan at two cells per lane stores q: same field
+    pi.pi_set_tile(plan.handle, 4, 2)
+    assert pi.pi_get_cg_recompute(plan.handle) == 0
+    res2 = plan.solve(g, tol=1e-9, max_iter=200000)
+    assert res2.status == 0, res2.info
+    assert rel_maxabs(np_(res2.P).astype(np.float64).ravel(), ref) <= 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("fixed_point", [False, True], ids=["paper_iteration", "fixed_point_variant"])
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_many_block_grid_takes_alpha_and_beta_from_a_finalize_kernel(fixed_point, lanes):
     """An instance of more than 1024 blocks (here 2113: 64 x 130 x 130 cells,
-    one cell per lane, two-plane segments) gets the CG scalars from a
-    finalize kernel after each pass instead of re-summing the partials in
-    every block; both routes must reach the oracle's fixed point."""
+    one or four cells per lane (one wave per row either way), two-plane
+    segments) gets the CG scalars from a finalize kernel after each pass
+    instead of re-summing the partials in every block; both routes must reach
+    the oracle's fixed point.  At four cells per lane the passes evaluate q
+    again (two kernels per pass before the finalize)."""
     import paper_2311_16935_amd as pi
     from oracle.solve import fixed_point_cg
 
@@ -464,7 +501,8 @@ def test_many_block_grid_takes_alpha_and_beta_from_a_finalize_kernel(fixed_point
     w = synth.random_small(71, 3, (64, 130, 130), anisotropic=False, mask_frac=0.0)
     g = _grads(w, False)
     plan = pi.Plan(w.dims, w.spacing, fixed_point=fixed_point)
-    pi.pi_set_tile(plan.handle, 2, 1)
+    pi.pi_set_tile(plan.handle, 2, lanes)
+    assert pi.pi_get_cg_recompute(plan.handle) == (1 if lanes == 4 else 0)
     waves = 1 * 130 * 65
     assert (waves + 3) // 4 > 1024
     res = plan.solve(g, tol=1e-9, max_iter=200000)
