@@ -894,8 +894,9 @@ def main():
         dom_name = kern_names.get(dom, dom)
         traffic = traffic_from_profile(dom_name, n, src_hash, "lamb_cc")
     else:
-        dom_name = dom
-        traffic = traffic_from_profile(dom, n, src_hash) if args.workload == "blobs3d" else None
+        # a plan whose CG passes evaluate q again runs them as k_cg_rq
+        dom_name = "k_cg_rq" if dom == "k_cg_step" and pi.pi_get_cg_recompute(plan.handle) else dom
+        traffic = traffic_from_profile(dom_name, n, src_hash) if args.workload == "blobs3d" else None
     roof = {"kernel": dom_name, "bound": "hbm", "achieved": d["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": d["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic,
             "bytes_per_cell": bytes_per_cell[dom], "cells_per_launch": ncell}

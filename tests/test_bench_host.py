@@ -29,14 +29,15 @@ def test_traffic_is_read_only_from_a_summary_of_the_current_source(tmp_path):
     h = b.kernel_source_hash()
     assert len(h) == 16 and h == b.kernel_source_hash()
     # the committed summaries carry the hash of the source they were taken on
-    for n in (256, 500):
-        path = os.path.join(ROOT, "profiles", f"k_cg_step_blobs{n}_pmc.txt")
+    # (the 256^3 CG pass evaluates q again: k_cg_rq; 500^3 rows span two strips: k_cg_step)
+    for kernel, n in (("k_cg_rq", 256), ("k_cg_step", 500)):
+        path = os.path.join(ROOT, "profiles", f"{kernel}_blobs{n}_pmc.txt")
         txt = open(path).read()
         stated = [ln.split(":", 1)[1].strip() for ln in txt.splitlines() if ln.startswith("source_sha256:")]
         hbm = [float(ln.split(":", 1)[1]) for ln in txt.splitlines() if ln.startswith("hbm_bytes_per_launch:")]
         assert len(stated) == 1 and len(hbm) == 1
-        got = b.traffic_from_profile("k_cg_step", n, stated[0])
+        got = b.traffic_from_profile(kernel, n, stated[0])
         assert got == hbm[0]
         # any other source: no traffic figure
-        assert b.traffic_from_profile("k_cg_step", n, "0" * 16) is None
+        assert b.traffic_from_profile(kernel, n, "0" * 16) is None
     assert b.traffic_from_profile("k_cg_step", 123, h) is None
