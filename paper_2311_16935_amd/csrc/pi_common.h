@@ -141,8 +141,8 @@ struct Inst {
                     // pass's partials themselves (no finalize kernel)
   int32_t nt_outer; // the outer kernel streams S, P' and r non-temporally
                     // (chosen by the autotuner)
-  int32_t cg_rq;    // host side: the plan's CG passes evaluate q again
-                    // instead of storing it (launch_cg_rq)
+  int32_t cg_rq;    // the plan's CG passes evaluate q again instead of
+                    // storing it (launch_cg_rq; 0 in batched launches)
   int32_t cg_slots; // partial-sum slots of a CG pass: nblocks, plus the
                     // boundary-layer blocks of k_cg_rq
   int32_t ncomp;    // connected groups of data cells

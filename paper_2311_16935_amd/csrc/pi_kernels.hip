@@ -922,6 +922,8 @@ struct CgPass {
   bool skip;
 };
 
+__device__ inline bool rq_p0_is_r(const Inst &in) { return in.cg_rq && in.inner_op == 0 && in.inner_iters >= 2; }
+
 template <typename T>
 __device__ inline CgPass<T> cg_pass(const Inst &in, State *st, const double *part, int lb, int k) {
   CgPass<T> c;
@@ -959,7 +961,11 @@ __device__ inline CgPass<T> cg_pass(const Inst &in, State *st, const double *par
   c.rnew = gp<T>(o ? in.res1 : in.res);
   c.qold = gp<T>(o ? in.q1 : in.q);
   c.qnew = gp<T>(o ? in.q : in.q1);
-  c.pold = gp<T>(in.p[o]);
+  // p_0 = r_0: a plan whose later passes evaluate q again takes p_0 from
+  // the residual in pass 1, so pass 0 stores neither p nor q (the paper's
+  // iteration with at least two passes: its last pass, which the outer
+  // kernel folds in, is then never pass 0)
+  c.pold = gp<T>(k == 1 && rq_p0_is_r(in) ? in.res : in.p[o]);
   c.pnew = gp<T>(in.p[o ^ 1]);
   c.d = gp<T>(in.d);
   c.al = (T)al;
@@ -1052,6 +1058,7 @@ __device__ __forceinline__ void cg_step_body(const BlockEnt *tab, const Inst *__
       for (int k = 0; k < W; ++k) x.e[k] = Aux{r.e[k], T(0)};
       return x;
     };
+    const bool keep = !rq_p0_is_r(in);  // uniform over the launch
     auto store0 = [&](int64_t c, const Out (&o)[W]) {
       Vec<T, W> pv, qv;
 #pragma unroll
@@ -1059,8 +1066,10 @@ __device__ __forceinline__ void cg_step_body(const BlockEnt *tab, const Inst *__
         pv.e[k] = o[k].p;
         qv.e[k] = o[k].q;
       }
-      stv_nt<W>(cg.pnew, c, pv);
-      stv_nt<W>(cg.qnew, c, qv);
+      if (keep) {
+        stv_nt<W>(cg.pnew, c, pv);
+        stv_nt<W>(cg.qnew, c, qv);
+      }
     };
     march<ND, W, GEN, T, Aux, Out>(wk, load0, load01, aux0, body, store0);
   } else {
@@ -1157,6 +1166,28 @@ __device__ inline void xnb0(const Vec<T, W> &v, int lane, T (&vW)[W], T (&vE)[W]
     vW[k] = k == 0 ? left : v.e[k > 0 ? k - 1 : 0];
     vE[k] = k == W - 1 ? right : v.e[k + 1 < W ? k + 1 : 0];
   }
+}
+
+// Class of coordinate c on an axis of n cells as the counter code sees it:
+// min(c, 2) + 3 min(n - 1 - c, 2) (whether the cells one and two steps away
+// on each side lie in the grid).  The code of a cell of a grid without
+// missing data is a function of its three classes (729 of them).
+__device__ inline int rq_cls(int c, int n) { return min(c, 2) + 3 * min(n - 1 - c, 2); }
+// Fill the code table in LDS: entry cx + 9 cy + 81 cz is the code of a cell
+// with those classes (a representative cell c = min(c, 2) on an axis of
+// c + 1 + min(n - 1 - c, 2) cells has the same neighbours in the grid).
+__device__ inline void rq_code_table(uint32_t *ctab) {
+  for (int i = threadIdx.x; i < 729; i += kBlock) {
+    const int cl[3] = {i % 9, (i / 9) % 9, i / 81};
+    int c[3], n[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      c[ax] = cl[ax] % 3;
+      n[ax] = c[ax] + 1 + cl[ax] / 3;
+    }
+    ctab[i] = code_at<3>(c[0], c[1], c[2], n[0], n[1], n[2]);
+  }
+  __syncthreads();
 }
 
 // The interior planes of a wave: [i0, i1), empty unless the
@@ -1291,7 +1322,8 @@ __device__ inline void rq_int_march(const Inst &in, const CgPass<float> &cg, con
 // checked.
 template <int W, bool OPL>
 __device__ inline void rq_bnd_march(const Inst &in, const CgPass<float> &cg, const Walk &wk, const float (*lut)[kStates],
-                                    const float *wi, const float *a, int a0, int a1, double (&acc)[4]) {
+                                    const uint32_t *ctab, const float *wi, const float *a, int a0, int a1,
+                                    double (&acc)[4]) {
   using T = float;
   if (a0 >= a1) return;  // uniform over the wave
   const int lane = threadIdx.x & 63;
@@ -1307,11 +1339,15 @@ __device__ inline void rq_bnd_march(const Inst &in, const CgPass<float> &cg, con
   auto cj = [&](int j) { return wk.base + (int64_t)min(max(j, 0), nm - 1) * sm; };
   auto inp = [&](int j) { return j >= 0 && j < nm; };
   auto ldz = [&](const PI_G T *arr, int64_t c, bool ok) { return ok ? ldv<W>(arr, c) : z; };
+  // codes from the class table: x class per cell (fixed), y class per row, z class per plane
+  int cxk[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) cxk[k] = rq_cls(min(wk.x + k, wk.nx - 1), wk.nx);
   auto codes = [&](int j, int row) {
+    const int cyz = 9 * rq_cls(min(max(row, 0), wk.ny - 1), wk.ny) + 81 * rq_cls(min(max(j, 0), nm - 1), nm);
     Vec<uint32_t, W> v;
 #pragma unroll
-    for (int k = 0; k < W; ++k)
-      v.e[k] = code_at<3>(min(wk.x + k, wk.nx - 1), row, min(max(j, 0), nm - 1), wk.nx, wk.ny, wk.nz);
+    for (int k = 0; k < W; ++k) v.e[k] = ctab[cxk[k] + cyz];
     return v;
   };
   auto tl = [&](int d, int st) { return lut[d][st]; };
@@ -1449,7 +1485,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_rq(const BlockEnt *tab, const Ins
     rq_int_march<W, OPL>(in, cg, make_walk<W>(in, e.lb), acc);
   } else {
     __shared__ T lut[6][kStates];
+    __shared__ uint32_t ctab[729];
     load_lut<T>(in.lut_np1, lut);
+    rq_code_table(ctab);
     T wi[6], a[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
@@ -1459,7 +1497,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_rq(const BlockEnt *tab, const Ins
     int row, a0, a1;
     const int64_t t = (int64_t)(e.lb - in.nblocks) * kWavesPerBlock + (threadIdx.x >> 6);
     if (rq_task(in, t, row, a0, a1))  // uniform over the wave
-      rq_bnd_march<W, OPL>(in, cg, rq_walk<W>(in, row, a0, a1), lut, wi, a, a0, a1, acc);
+      rq_bnd_march<W, OPL>(in, cg, rq_walk<W>(in, row, a0, a1), lut, ctab, wi, a, a0, a1, acc);
   }
   publish<4>(in, cg_part(in, part, kpass), e.lb, acc);
 }

@@ -424,7 +424,8 @@ pi_status batch_setup(int64_t count, const pi_plan_t *plans, const void *const *
   b.cg_finalize = false;
   for (auto &h : b.host) {
     h.part_stride = b.parts;
-    h.cg_slots = h.nblocks;  // batched launches store q
+    h.cg_rq = 0;  // batched launches store q
+    h.cg_slots = h.nblocks;
     h.cg_inline = h.nblocks <= kInlineMaxBlocks ? 1 : 0;
     if (!b.bicg && !h.cg_inline) b.cg_finalize = true;
   }
