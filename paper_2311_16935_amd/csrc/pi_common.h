@@ -44,7 +44,7 @@ constexpr int32_t kNoStop = 1 << 30;
 // next to the march faces (planes 0..2 and nm-3..nm-1 of the other rows) are
 // wave tasks of blocks of their own; the rest is interior.  With ny or nm
 // below 7 there is no interior and every row is a boundary row.
-constexpr int kRqChunk = 4;
+constexpr int kRqChunk = 3;
 __host__ __device__ inline int64_t rq_ntasks(int ny, int nm) {
   const bool inner = ny >= 7 && nm >= 7;
   const int64_t nA = (int64_t)(inner ? 6 : ny) * ((nm + kRqChunk - 1) / kRqChunk);
