@@ -306,8 +306,10 @@ pi_status pi_time_kernel(pi_plan_t plan, int kernel, int32_t reps, double *avg_m
  * iterates are the same bit for bit; a pass then moves 24 bytes per cell
  * (reads r, p and the correction, writes them) instead of 32.  Chosen for
  * 3-D FP32 CG plans without missing data at four cells per lane whose rows
- * fit one wave strip (nx <= 256); it follows the tile, so read it after
- * pi_set_tile or pi_autotune.
+ * fit one wave strip (nx <= 256) or split over as many overlapping wave
+ * windows (owning 252 cells at the row ends, 248 between them) as 256-cell
+ * strips: every nx up to 504 and most longer ones, 512 not; it follows the
+ * tile, so read it after pi_set_tile or pi_autotune.
  */
 int32_t pi_get_cg_recompute(pi_plan_t plan);
 

@@ -42,13 +42,38 @@ constexpr int32_t kNoStop = 1 << 30;
 // CG passes that evaluate q again (k_cg_rq): the layers next to the y faces
 // (rows 0..2 and ny-3..ny-1, every plane, in chunks of kRqChunk planes) and
 // next to the march faces (planes 0..2 and nm-3..nm-1 of the other rows) are
-// wave tasks of blocks of their own; the rest is interior.  With ny or nm
-// below 7 there is no interior and every row is a boundary row.
+// wave tasks of blocks of their own, for every wave strip of the row; the
+// rest is interior.  With ny or nm below 7 there is no interior and every
+// row is a boundary row.
 constexpr int kRqChunk = 3;
-__host__ __device__ inline int64_t rq_ntasks(int ny, int nm) {
+__host__ __device__ inline int64_t rq_ntasks(int ny, int nm, int nxs) {
   const bool inner = ny >= 7 && nm >= 7;
   const int64_t nA = (int64_t)(inner ? 6 : ny) * ((nm + kRqChunk - 1) / kRqChunk);
-  return nA + (inner ? 2 * (int64_t)(ny - 6) : 0);
+  return (nA + (inner ? 2 * (int64_t)(ny - 6) : 0)) * nxs;
+}
+// A row longer than one wave strip (64 lanes of four cells, kRqSpan cells)
+// is split over overlapping wave windows: q_k at a cell needs p_{k-1} two
+// cells away along x, which a window evaluates correctly only two cells or
+// more inside its edges, so each window owns (stores and sums) the cells at
+// least one lane (four cells) inside every edge that is not a grid face.
+// The first window owns [0, kRqSpan - 4), the middle ones kRqSpan - 8 cells
+// each, the last the rest; window xs starts four cells before its owned
+// range, or at nx - kRqSpan where that is earlier.  Rows need nx % 4 == 0.
+constexpr int kRqSpan = 256;
+__host__ __device__ inline int rq_nstrips(int nx) {
+  if (nx <= kRqSpan) return 1;
+  const int rest = nx - 2 * (kRqSpan - 4);
+  return 2 + (rest > 0 ? (rest + kRqSpan - 9) / (kRqSpan - 8) : 0);
+}
+__host__ __device__ inline void rq_window(int nx, int nxs, int xs, int &start, int &own0, int &own1) {
+  if (nxs == 1) {
+    start = own0 = 0;
+    own1 = nx;
+    return;
+  }
+  own0 = xs == 0 ? 0 : (kRqSpan - 4) + (kRqSpan - 8) * (xs - 1);
+  own1 = xs == nxs - 1 ? nx : (kRqSpan - 4) + (kRqSpan - 8) * xs;
+  start = xs == 0 ? 0 : (own0 - 4 < nx - kRqSpan ? own0 - 4 : nx - kRqSpan);
 }
 constexpr int kShapeCC4 = 13;
 

@@ -1427,11 +1427,14 @@ __device__ inline void rq_bnd_march(const Inst &in, const CgPass<float> &cg, con
   }
 }
 
-// Boundary-layer task t (rq_ntasks of them) -> row and planes [a, b): the
-// rows next to the y faces in chunks of kRqChunk planes, then for every
-// other row the three planes next to each march face; false past the last.
-__device__ inline bool rq_task(const Inst &in, int64_t t, int &row, int &a, int &b) {
+// Boundary-layer task t (rq_ntasks of them) -> wave strip, row and planes
+// [a, b): the rows next to the y faces in chunks of kRqChunk planes, then for
+// every other row the three planes next to each march face; false past the
+// last.
+__device__ inline bool rq_task(const Inst &in, int64_t t, int &xs, int &row, int &a, int &b) {
   const int ny = in.ny, nm = in.nm;
+  xs = (int)(t % in.nxs);
+  t /= in.nxs;
   const bool inner = ny >= 7 && nm >= 7;
   const int nbr = inner ? 6 : ny;
   const int nch = (nm + kRqChunk - 1) / kRqChunk;
@@ -1451,9 +1454,22 @@ __device__ inline bool rq_task(const Inst &in, int64_t t, int &row, int &a, int 
   return true;
 }
 
-// A wave's view of a task: the one strip of row `row`, planes [m0, m1).
+// Place a wave on its window of strip xs of row `row` (rq_window): lanes of
+// a single-strip row past its end address the row's last cells and own
+// nothing; in a split row every lane is inside the grid and owns its cells
+// when they lie in the strip's owned range.
 template <int W>
-__device__ inline Walk rq_walk(const Inst &in, int row, int m0, int m1) {
+__device__ inline void rq_place(const Inst &in, int xs, int row, Walk &k) {
+  int start, own0, own1;
+  rq_window(in.nx, in.nxs, xs, start, own0, own1);
+  k.x = start + (threadIdx.x & 63) * W;
+  k.act = k.x >= own0 && k.x < own1;
+  k.base = (int64_t)min(k.x, in.nx - W) + (int64_t)row * in.srow;
+}
+
+// A wave's view of a task: strip xs of row `row`, planes [m0, m1).
+template <int W>
+__device__ inline Walk rq_walk(const Inst &in, int xs, int row, int m0, int m1) {
   Walk k;
   k.sm = in.sm;
   k.code = gp<uint32_t>(in.code);
@@ -1461,12 +1477,20 @@ __device__ inline Walk rq_walk(const Inst &in, int row, int m0, int m1) {
   k.nx = in.nx;
   k.ny = in.ny;
   k.nz = in.nz;
-  k.x = (threadIdx.x & 63) * W;
   k.m0 = m0;
   k.m1 = m1;
   k.row = row;
-  k.act = k.x < in.nx;
-  k.base = (int64_t)min(k.x, in.nx - W) + (int64_t)row * in.srow;
+  rq_place<W>(in, xs, row, k);
+  return k;
+}
+
+// The interior walk of block lb: the generic walk (make_walk) with the
+// wave moved to its window.
+template <int W>
+__device__ inline Walk rq_iwalk(const Inst &in, int lb) {
+  Walk k = make_walk<W>(in, lb);
+  const int64_t w = (int64_t)lb * kWavesPerBlock + (threadIdx.x >> 6);
+  if (w < in.nwaves && in.nxs > 1) rq_place<W>(in, (int)(w % in.nxs), k.row, k);
   return k;
 }
 
@@ -1482,7 +1506,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_rq(const BlockEnt *tab, const Ins
   if (cg.skip) return;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (e.lb < in.nblocks) {  // uniform over the block
-    rq_int_march<W, OPL>(in, cg, make_walk<W>(in, e.lb), acc);
+    rq_int_march<W, OPL>(in, cg, rq_iwalk<W>(in, e.lb), acc);
   } else {
     __shared__ T lut[6][kStates];
     __shared__ uint32_t ctab[729];
@@ -1494,10 +1518,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_rq(const BlockEnt *tab, const Ins
       wi[d] = (T)in.lut_np1[d][interior_state<3>()];
       a[d] = (T)in.a[d];
     }
-    int row, a0, a1;
+    int xs, row, a0, a1;
     const int64_t t = (int64_t)(e.lb - in.nblocks) * kWavesPerBlock + (threadIdx.x >> 6);
-    if (rq_task(in, t, row, a0, a1))  // uniform over the wave
-      rq_bnd_march<W, OPL>(in, cg, rq_walk<W>(in, row, a0, a1), lut, ctab, wi, a, a0, a1, acc);
+    if (rq_task(in, t, xs, row, a0, a1))  // uniform over the wave
+      rq_bnd_march<W, OPL>(in, cg, rq_walk<W>(in, xs, row, a0, a1), lut, ctab, wi, a, a0, a1, acc);
   }
   publish<4>(in, cg_part(in, part, kpass), e.lb, acc);
 }

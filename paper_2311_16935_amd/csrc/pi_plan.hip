@@ -444,15 +444,17 @@ hipError_t plan_tables(pi_plan_s *p) {
   // three partial-sum arrays: the outer-step kernels', and one per parity
   // of the inner CG passes
   // CG passes without a stored q: 3-D, no missing data, FP32, four cells per
-  // lane and one wave strip per row.  Their boundary-layer blocks come first
+  // lane, and rows whose overlapping wave windows (rq_nstrips) are as many as
+  // the plan's wave strips, so the interior blocks keep the plan's table.
+  // Their boundary-layer blocks come first
   // in the CG passes' table (dispatched first, they run beside the interior
   // blocks) and have partial-sum slots of their own after the others.
   p->inst.cg_rq = (p->ndim == 3 && p->inst.gen && !p->fp64 && !p->bicgstab && !p->cc && p->inst.vw == 4 &&
-                   p->inst.nxs == 1)
+                   p->inst.nxs == rq_nstrips(p->inst.nx))
                       ? 1
                       : 0;
   const int nbnd =
-      p->inst.cg_rq ? (int)((rq_ntasks(p->inst.ny, p->inst.nm) + kWavesPerBlock - 1) / kWavesPerBlock) : 0;
+      p->inst.cg_rq ? (int)((rq_ntasks(p->inst.ny, p->inst.nm, p->inst.nxs) + kWavesPerBlock - 1) / kWavesPerBlock) : 0;
   p->inst.cg_slots = p->inst.nblocks + nbnd;
   p->inst.part_stride = std::max(parts, p->inst.cg_slots);
   p->inst.cg_inline = p->inst.cg_slots <= kInlineMaxBlocks ? 1 : 0;

@@ -452,14 +452,16 @@ def test_fixed_point_cg_variant_reaches_the_same_field(name, make, fp64):
 
 
 @pytest.mark.parametrize("fixed_point", [False, True], ids=["paper_iteration", "fixed_point_variant"])
-@pytest.mark.parametrize("dims", [(40, 23, 17), (32, 5, 6), (256, 9, 8)], ids=["interior_and_layers", "layers_only",
-                                                                              "full_strip"])
+@pytest.mark.parametrize("dims", [(40, 23, 17), (32, 5, 6), (256, 9, 8), (500, 9, 8), (260, 7, 9)],
+                         ids=["interior_and_layers", "layers_only", "full_strip", "split_row", "split_row_short_tail"])
 def test_cg_passes_that_evaluate_q_again(dims, fixed_point):
-    """3-D FP32 grids without missing data at four cells per lane, rows of at
-    most 256 cells: the CG passes after the first evaluate q = M p again
-    instead of reading it (an interior kernel and a boundary-layer kernel).
-    The converged field must match the oracle's fixed point; (32, 5, 6) has
-    no interior rows or planes, so the boundary kernel does all the work."""
+    """3-D FP32 grids without missing data at four cells per lane: the CG
+    passes after the first evaluate q = M p again instead of reading it
+    (interior blocks and boundary-layer blocks of one kernel).  The converged
+    field must match the oracle's fixed point; (32, 5, 6) has no interior
+    rows or planes, so the boundary tasks do all the work; rows of 500 and
+    260 cells are split over two overlapping wave windows (the second starts
+    at cell 244, resp. 4, and owns the cells from 252 on)."""
     import paper_2311_16935_amd as pi
     from oracle.solve import fixed_point_cg
 
@@ -482,6 +484,19 @@ def test_cg_passes_that_evaluate_q_again(dims, fixed_point):
     res2 = plan.solve(g, tol=1e-9, max_iter=200000)
     assert res2.status == 0, res2.info
     assert rel_maxabs(np_(res2.P).astype(np.float64).ravel(), ref) <= 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("nx,expect", [(256, 1), (260, 1), (504, 1), (508, 0), (512, 0), (752, 1), (756, 0)])
+def test_which_row_lengths_evaluate_q_again(nx, expect):
+    """Rows split over overlapping wave windows evaluate q again only where
+    the windows are as many as the plan's 256-cell strips (first window 252
+    owned cells, middle ones 248, last up to 252)."""
+    import paper_2311_16935_amd as pi
+
+    plan = pi.Plan((nx, 7, 7), (1.0, 1.0, 1.0))
+    pi.pi_set_tile(plan.handle, 4, 4)
+    assert pi.pi_get_cg_recompute(plan.handle) == expect
     plan.close()
 
 
