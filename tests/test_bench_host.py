@@ -29,8 +29,8 @@ def test_traffic_is_read_only_from_a_summary_of_the_current_source(tmp_path):
     h = b.kernel_source_hash()
     assert len(h) == 16 and h == b.kernel_source_hash()
     # the committed summaries carry the hash of the source they were taken on
-    # (the 256^3 CG pass evaluates q again: k_cg_rq; 500^3 rows span two strips: k_cg_step)
-    for kernel, n in (("k_cg_rq", 256), ("k_cg_step", 500)):
+    # (the CG passes evaluate q again at both sizes: k_cg_rq)
+    for kernel, n in (("k_cg_rq", 256), ("k_cg_rq", 500)):
         path = os.path.join(ROOT, "profiles", f"{kernel}_blobs{n}_pmc.txt")
         txt = open(path).read()
         stated = [ln.split(":", 1)[1].strip() for ln in txt.splitlines() if ln.startswith("source_sha256:")]
