@@ -1048,11 +1048,15 @@ __device__ __forceinline__ void cg_step_body(const BlockEnt *tab, const Inst *__
     if (cg.wr_d) stv_nt<W>(cg.d, c, dv);
   };
   if constexpr (FIRST) {
-    // p_0 = r_0: only the residual is read; p and q are written
+    // p_0 = r_0: only the residual is read; p and q are written.  Few bytes
+    // per cell, so the loads of two planes ahead stay in flight (march2).
     auto load0 = [&](int64_t c) { return ldv<W>(cg.rold, c); };
     auto load01 = [&](int64_t c) -> T { return cg.rold[c]; };
-    auto aux0 = [&](int64_t c) {
-      const Vec<T, W> r = ldv<W>(cg.rold, c);
+    struct None {};
+    auto extra0 = [](int64_t) { return None{}; };
+    auto cookv0 = [](const Vec<T, W> &v) { return v; };
+    auto cook10 = [](T v) { return v; };
+    auto cooka0 = [](const Vec<T, W> &r, None) {
       Vec<Aux, W> x;
 #pragma unroll
       for (int k = 0; k < W; ++k) x.e[k] = Aux{r.e[k], T(0)};
@@ -1071,7 +1075,7 @@ __device__ __forceinline__ void cg_step_body(const BlockEnt *tab, const Inst *__
         stv_nt<W>(cg.qnew, c, qv);
       }
     };
-    march<ND, W, GEN, T, Aux, Out>(wk, load0, load01, aux0, body, store0);
+    march2<ND, W, GEN, T, Aux, Out>(wk, load0, load01, extra0, cookv0, cook10, cooka0, body, store0);
   } else {
     march<ND, W, GEN, T, Aux, Out>(wk, load, load1, aux, body, store);
   }

@@ -777,18 +777,19 @@ out:
   return rc;
 }
 
-// Per-pass cost of an inner CG pass as a solve runs it: kCgPassesTimed
+// Per-pass cost of inner CG pass `kpass` (0: the first of an outer step,
+// which reads only the residual; 2: one of the later passes) as a solve runs
+// it: kCgPassesTimed
 // passes, each with its finalize kernel where the tile needs one, captured
 // in a HIP graph as the solve captures them and replayed (back-to-back
 // stream launches hide the cost of the graph's dependency between a pass
 // and its finalize).  The finalize moves the state on between passes; the
 // values do not change the amount of work.
 constexpr int kCgPassesTimed = 8;
-pi_status time_cg_pass(pi_plan_t p, int32_t reps, double *avg_ms, hipStream_t stream) {
+pi_status time_cg_pass(pi_plan_t p, int32_t reps, double *avg_ms, hipStream_t stream, int kpass) {
   pi_status rc = timing_state(p, stream);
   if (rc != PI_OK) return rc;
   const Launcher L = single_launcher(p);
-  const int kpass = 2;
   hipStream_t cap = cap_stream(p);
   hipGraph_t g = nullptr;
   hipGraphExec_t ge = nullptr;
@@ -857,11 +858,13 @@ extern "C" pi_status pi_autotune(pi_plan_t p, int32_t reps, int32_t *mseg_out, v
     auto step_ms = [&](const std::array<int32_t, 2> &c, int32_t r, double *ms) -> pi_status {
       pi_status e;
       if ((e = pi_set_tile(p, c[0], c[1])) != PI_OK) return e;
-      double t_outer = 0.0, t_inner = 0.0;
-      if ((e = pi_time_kernel(p, PI_K_OUTER, r, &t_outer, stream)) != PI_OK ||
-          (!p->bicgstab && (e = time_cg_pass(p, r, &t_inner, (hipStream_t)stream)) != PI_OK))
-        return e;
-      *ms = t_outer + p->inner_iters * t_inner;
+      double t_outer = 0.0, t_first = 0.0, t_inner = 0.0;
+      if ((e = pi_time_kernel(p, PI_K_OUTER, r, &t_outer, stream)) != PI_OK) return e;
+      if (!p->bicgstab && p->inner_iters > 0) {
+        if ((e = time_cg_pass(p, r, &t_first, (hipStream_t)stream, 0)) != PI_OK) return e;
+        if (p->inner_iters > 1 && (e = time_cg_pass(p, r, &t_inner, (hipStream_t)stream, 2)) != PI_OK) return e;
+      }
+      *ms = t_outer + t_first + std::max(0, p->inner_iters - 1) * t_inner;
       return PI_OK;
     };
     // every candidate once, then the three fastest again with four times the
