@@ -316,10 +316,11 @@ int32_t pi_get_cg_recompute(pi_plan_t plan);
 /*
  * pi_autotune -- pick the tile (pi_set_tile) that minimises the time of one
  * outer step of Algorithm 1 for this plan: for each candidate (segment
- * length, cells per lane) it times the outer kernel once and the inner CG
- * pass, with its finalize kernel where the tile needs one, `inner_iters`
- * times (`reps` launches each; the CG passes as a HIP graph of eight passes,
- * as a solve runs them), times the three fastest again with
+ * length, cells per lane) it times the outer kernel, the first inner CG pass
+ * of a step and a later one (`reps` launches each; the CG passes, with their
+ * finalize kernel where the tile needs one, as a HIP graph of eight passes,
+ * as a solve runs them), models a step as outer + first + (inner_iters - 1)
+ * later passes, times the three fastest again with
  * 4 * reps launches and keeps the fastest of those; then it chooses between
  * plain and non-temporal streams in the outer kernel (4 * reps launches each).  Results are
  * cached per (ndim, dims, precision, inner solver) for the life of the process,
