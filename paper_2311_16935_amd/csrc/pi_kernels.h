@@ -39,7 +39,8 @@ hipError_t launch(KernelId k, bool fp64, int shape, const LaunchArgs &la);
 
 // Inner CG pass k >= 1 without a stored q (k_cg_rq) for
 // one plan that qualifies (Inst.cg_rq): 3-D, no missing data, FP32, four
-// cells per lane, one wave strip per row.  opl: the fixed point's operator.
+// cells per lane, rows of one wave strip or of as many overlapping windows
+// as strips.  opl: the fixed point's operator.
 hipError_t launch_cg_rq(bool opl, const LaunchArgs &la);
 
 // Kernels that leave per-block partial sums, and the per-instance finalize

@@ -1096,8 +1096,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_step(const BlockEnt *tab, const I
 }
 
 // ---------------------------------------------------------------------------
-// The inner CG pass without a stored q: 3-D grids without missing data whose
-// rows fit one wave strip (four cells per lane), FP32.
+// The inner CG pass without a stored q: 3-D grids without missing data, four
+// cells per lane, FP32, rows of one wave strip or split over overlapping
+// wave windows (rq_window).
 //
 // CG's state is r, p and the correction; q = A p is stored only so that the
 // next pass can form r_k = r_{k-1} - alpha q_{k-1}.  Here q_{k-1} = A p_{k-1}
@@ -1157,8 +1158,9 @@ __device__ inline T op_w(const T (&w)[6], T vC, T vW, T vE, T vN, T vS, T vB, T 
   }
 }
 
-// x neighbours of a lane's W cells; the strip is the whole row, so beyond
-// its ends lies the grid face (0)
+// x neighbours of a lane's W cells; beyond the wave's ends reads 0: the grid
+// face where the window ends at one, else a cell the window does not own
+// (rq_window keeps owned cells far enough inside)
 template <typename T, int W>
 __device__ inline void xnb0(const Vec<T, W> &v, int lane, T (&vW)[W], T (&vE)[W]) {
   T left = __shfl_up(v.e[W - 1], 1, kWave);
