@@ -452,9 +452,10 @@ def test_fixed_point_cg_variant_reaches_the_same_field(name, make, fp64):
 
 
 @pytest.mark.parametrize("fixed_point", [False, True], ids=["paper_iteration", "fixed_point_variant"])
-@pytest.mark.parametrize("dims", [(40, 23, 17), (32, 5, 6), (256, 9, 8), (500, 9, 8), (260, 7, 9), (504, 11, 9)],
+@pytest.mark.parametrize("dims", [(40, 23, 17), (32, 5, 6), (256, 9, 8), (500, 9, 8), (260, 7, 9), (504, 11, 9),
+                                  (752, 8, 7)],
                          ids=["interior_and_layers", "layers_only", "full_strip", "split_row", "split_row_short_tail",
-                              "split_row_longest"])
+                              "split_row_longest", "split_row_three_windows"])
 def test_cg_passes_that_evaluate_q_again(dims, fixed_point):
     """3-D FP32 grids without missing data at four cells per lane: the CG
     passes after the first evaluate q = M p again instead of reading it
@@ -463,7 +464,8 @@ def test_cg_passes_that_evaluate_q_again(dims, fixed_point):
     rows or planes, so the boundary tasks do all the work; rows of 500, 260
     and 504 cells are split over two overlapping wave windows (the second
     starts at cell 244, 4 and 248 and owns the cells from 252 on; 504 is the
-    longest row two windows cover)."""
+    longest row two windows cover); a row of 752 takes three, the middle one
+    [248, 504) owning [252, 500)."""
     import paper_2311_16935_amd as pi
     from oracle.solve import fixed_point_cg
 
